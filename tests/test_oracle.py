@@ -1,0 +1,368 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+closed forms, lattice sums, crystallographic shell counts, the paper's worked
+DIL example, geometric special cases, invariants and brute force."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_cs_0702131_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_closed_forms():
+    vals = {}
+    for line in open(os.path.join(GOLD, "lj_closed_forms.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, v = line.split()
+            vals[k] = float(v)
+    return vals
+
+
+# ---------------------------------------------------------------- LJ closed forms (P1)
+
+
+def test_lj_closed_forms(oracle):
+    g = _golden_closed_forms()
+    rmin = 2.0 ** (1.0 / 6.0)
+    u, gg = oracle.lj(1.0)
+    assert abs(u - g["U_at_sigma"]) < 1e-14
+    assert abs(gg * 1.0 - g["F_at_sigma"]) < 1e-12          # |F| = g r at r = sigma
+    u, gg = oracle.lj(rmin * rmin)
+    assert abs(u - g["U_at_rmin"]) < 1e-14
+    assert abs(gg * rmin - g["F_at_rmin"]) < 1e-13
+    u, gg = oracle.lj(6.25)
+    assert abs(u - g["U_at_rcut"]) < 5e-9
+    assert abs(gg * 2.5 - g["F_at_rcut"]) < 5e-9
+    # U''(r_min) from a central difference of U(r)
+    h = 2e-5
+    upp = (oracle.lj((rmin + h) ** 2)[0] - 2 * oracle.lj(rmin ** 2)[0] + oracle.lj((rmin - h) ** 2)[0]) / h ** 2
+    assert abs(upp - g["U_second_derivative_at_rmin"]) < 5e-6
+
+
+def test_lj_mixing_and_scaling(oracle):
+    # Lorentz-Berthelot on a two-molecule system: eps_ab = sqrt(eps_a eps_b), sigma_ab = mean
+    x = np.array([[1.0, 1.0, 1.0], [2.1, 1.3, 0.8]])
+    d = x[0] - x[1]
+    s = d @ d
+    eps, sig = np.array([1.0, 0.5]), np.array([1.0, 0.88])
+    F, U, Wv, npairs = oracle.forces(x, [0, 1], eps, sig, 2.5, np.zeros((0, 3)))
+    e_ab, s_ab = math.sqrt(0.5), 0.94
+    # u(r) = 4 eps ((s/r)^12 - (s/r)^6) at the mixed parameters, via the single-species call
+    u1, g1 = oracle.lj(s / s_ab ** 2)          # eps = sigma = 1 at scaled distance
+    assert npairs == 1
+    assert abs(U - e_ab * u1) < 1e-13
+    assert np.allclose(F[0], e_ab * g1 / s_ab ** 2 * d, rtol=1e-13, atol=0)
+    assert np.allclose(F[0] + F[1], 0.0, atol=1e-14)
+    assert abs(Wv - e_ab * g1 / s_ab ** 2 * s) < 1e-13
+
+
+def test_two_molecules_across_periodic_face(oracle):
+    L = 10.0
+    lat = np.eye(3) * L
+    x = np.array([[0.3, 5.0, 5.0], [9.6, 5.0, 5.0]])      # 0.7 apart through x = 0
+    F, U, Wv, npairs = oracle.forces(x, [0, 0], [1.0], [1.0], 2.5, lat)
+    u, g = oracle.lj(0.7 ** 2)
+    assert npairs == 1
+    assert abs(U - u) < 1e-13 * abs(u)
+    assert np.allclose(F[0], [g * 0.7, 0, 0], rtol=1e-12)
+    assert np.allclose(F[1], [-g * 0.7, 0, 0], rtol=1e-12)
+    # three molecules: a chain through the corner image
+    x3 = np.array([[0.2, 0.2, 0.2], [9.9, 9.9, 9.9], [5.0, 5.0, 5.0]])
+    F3, U3, _, n3 = oracle.forces(x3, [0, 0, 0], [1.0], [1.0], 2.5, lat)
+    d = np.array([0.3, 0.3, 0.3])
+    u, g = oracle.lj(d @ d)
+    assert n3 == 1 and abs(U3 - u) < 1e-13 * abs(u)
+    assert np.allclose(F3[0], g * d, rtol=1e-12) and np.allclose(F3[2], 0)
+
+
+# ---------------------------------------------------------------- FCC lattice sums (P3)
+
+FCC_SHELLS = [(1, 12), (2, 6), (3, 24), (4, 12), (5, 24), (6, 8), (7, 48), (8, 6)]   # (k, count) at a*sqrt(k/2)
+
+
+def _fcc_closed_form(a, rc):
+    U = Wv = 0.0
+    nb = 0
+    for k, cnt in FCC_SHELLS:
+        r = a * math.sqrt(k / 2.0)
+        if r < rc:
+            sr6 = r ** -6
+            U += 0.5 * cnt * 4.0 * (sr6 * sr6 - sr6)
+            Wv += 0.5 * cnt * 24.0 * (2.0 * sr6 * sr6 - sr6)     # g(s) s = 24 (2 r^-12 - r^-6)
+            nb += cnt
+    return U, Wv, nb
+
+
+def test_fcc_lattice_sum_matches_shells(oracle):
+    L = 10.08
+    a = L / 6
+    x = W.fcc_sites((6, 6, 6), a)
+    F, U, Wv, npairs = oracle.forces(x, np.zeros(len(x), np.int32), [1.0], [1.0], 2.5, np.eye(3) * L)
+    Uc, Wc, nb = _fcc_closed_form(a, 2.5)
+    N = len(x)
+    assert N == 864 and nb == 54 and npairs == 54 * N // 2 == 23328
+    assert abs(U / N - Uc) < 1e-12 * abs(Uc)
+    assert abs(Wv / N - Wc) < 1e-12 * abs(Wc)
+    # the values quoted for this lattice (closed-form lattice sum at a = 1.68)
+    assert abs(U / N - (-6.7680388585)) < 1e-9
+    assert abs(Wv / N - (-22.1794622011)) < 1e-9
+    assert np.abs(F).max() < 1e-12   # inversion symmetry
+
+
+# ---------------------------------------------------------------- invariants
+
+
+def test_newton_and_min_image(oracle):
+    wl = W.small_random(N=150, seed=11, species_frac=0.7)
+    lat = wl.mesh.periodic
+    F, U, Wv, npairs = oracle.forces(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, lat)
+    scale = np.abs(F).sum()
+    assert np.abs(F.sum(axis=0)).max() < 1e-14 * scale
+    # minimum image written independently (rc < L/2)
+    L = np.diag(lat)
+    x = wl.x
+    d = x[:, None, :] - x[None, :, :]
+    d -= np.round(d / L) * L
+    s = (d ** 2).sum(-1)
+    np.fill_diagonal(s, np.inf)
+    sp = wl.species
+    e = np.sqrt(wl.eps[sp][:, None] * wl.eps[sp][None, :])
+    sg = 0.5 * (wl.sigma[sp][:, None] + wl.sigma[sp][None, :])
+    inr = s < wl.rcut ** 2
+    sr6 = np.where(inr, (sg * sg / s) ** 3, 0.0)
+    g = np.where(inr, 24 * e * (2 * sr6 * sr6 - sr6) / s, 0.0)
+    u = np.where(inr, 4 * e * (sr6 * sr6 - sr6), 0.0)
+    Fm = (g[:, :, None] * d).sum(1)
+    assert np.allclose(F, Fm, rtol=0, atol=1e-12 * np.abs(Fm).max())
+    assert abs(U - 0.5 * u.sum()) < 1e-12 * abs(U)
+    assert npairs == inr.sum() // 2
+
+
+def test_pairs_bruteforce(oracle):
+    wl = W.small_random(N=60, seed=3)
+    P = oracle.pairs(wl.x, wl.rcut, wl.mesh.periodic)
+    L = np.diag(wl.mesh.periodic)
+    ref = []
+    for a in range(len(wl.x)):
+        for b in range(a + 1, len(wl.x)):
+            for n in np.ndindex(3, 3, 3):
+                n = np.array(n) - 1
+                d = wl.x[a] - wl.x[b] - n * L
+                if d @ d < wl.rcut ** 2:
+                    ref.append((a, b, *n))
+    ref = np.array(sorted(ref), dtype=np.int64)
+    assert np.array_equal(P, ref)
+    _, _, _, npairs = oracle.forces(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic)
+    assert npairs == len(P)
+
+
+# ---------------------------------------------------------------- geometry pins
+
+
+def test_cell_distance_special_cases(oracle):
+    nodes = np.arange(4.0)
+    m = W.hex_mesh(nodes, nodes, nodes)           # 3x3x3 unit cubes, cell i + 3 j + 9 k
+    c = lambda i, j, k: i + 3 * (j + 3 * k)
+    assert oracle.cell_distance(m, c(0, 0, 0), c(1, 0, 0)) == 0.0
+    assert abs(oracle.cell_distance(m, c(0, 0, 0), c(2, 0, 0)) - 1.0) < 1e-15
+    assert abs(oracle.cell_distance(m, c(0, 0, 0), c(2, 2, 0)) - math.sqrt(2)) < 1e-15
+    assert abs(oracle.cell_distance(m, c(0, 0, 0), c(2, 2, 2)) - math.sqrt(3)) < 1e-15
+    assert abs(oracle.cell_distance(m, c(0, 0, 0), c(2, 1, 0)) - 1.0) < 1e-15
+    # shifted copy: cell (0,0,0) vs cell (2,0,0) moved by +10 x -> gap 11
+    assert abs(oracle.cell_distance(m, c(0, 0, 0), c(2, 0, 0), (10.0, 0, 0)) - 11.0) < 1e-13
+    # edge-to-edge skew configuration: cube at (0,0,0) vs cube (2,0,2) shifted (0, 0.5, 0)
+    assert abs(oracle.cell_distance(m, c(0, 0, 0), c(2, 0, 2), (0, 0.5, 0)) - math.sqrt(2)) < 1e-14
+
+
+def test_point_location_uniform(oracle):
+    nodes = np.linspace(0, 6.0, 4)
+    m = W.hex_mesh(nodes, nodes, nodes, shuffle_seed=4)
+    base = W.hex_mesh(nodes, nodes, nodes)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.01, 5.99, size=(300, 3))
+    ijk = np.floor(x / 2.0).astype(int)
+    struct = ijk[:, 0] + 3 * (ijk[:, 1] + 3 * ijk[:, 2])
+    # shuffled index of structured cell s: owner of the same face in both meshes
+    new_of_old = np.zeros(27, int)
+    new_of_old[base.owner] = m.owner
+    got = oracle.locate(m, x)
+    assert np.array_equal(got, new_of_old[struct])
+    # outside the mesh -> -1
+    assert oracle.locate(m, np.array([[7.0, 1.0, 1.0]]))[0] == -1
+    # on a shared face: lowest index of the two cells wins
+    p = np.array([[2.0, 1.0, 1.0]])
+    a, b = new_of_old[0], new_of_old[1]
+    assert oracle.locate(m, p)[0] == min(a, b)
+
+
+def test_jittered_mesh_is_valid_and_located(oracle):
+    wl = W.small_random(N=200, seed=9)
+    assert oracle.min_tet_volume(wl.mesh) > 0
+    cells = oracle.locate(wl.mesh, wl.x)
+    assert (cells >= 0).all()
+
+
+# ---------------------------------------------------------------- DIL pins (P5, P6)
+
+
+def _nc_closed_form(ratio):
+    r2 = ratio * ratio
+    cnt = 0
+    for a in range(-5, 6):
+        for b in range(-5, 6):
+            for c in range(-5, 6):
+                s = sum(max(abs(v) - 1, 0) ** 2 for v in (a, b, c))
+                if s < r2:
+                    cnt += 1
+    return cnt
+
+
+@pytest.mark.parametrize("ratio,nc", [(1.0, 27), (1.25, 81), (1.5625, 117), (1.914, 125), (2.0, 125), (2.5, 275)])
+def test_dil_counts_on_uniform_cubes(oracle, ratio, nc):
+    assert _nc_closed_form(ratio) == nc
+    nodes = np.arange(7.0)          # 6^3 unit cubes, periodic
+    m = W.hex_mesh(nodes, nodes, nodes, periodic_axes=(0, 1, 2), shuffle_seed=2)
+    D = oracle.dil(m, ratio, 0.0)
+    assert len(D) == m.n_cells * (nc - 1) // 2
+    # no cell on its own list with a zero image; (c,c,n) only with n > 0
+    same = D[D[:, 0] == D[:, 1]]
+    assert not np.any((same[:, 2:] == 0).all(axis=1))
+    assert np.all(D[:, 0] <= D[:, 1])
+
+
+def test_dil_k5_worked_example(oracle):
+    table = {}
+    for line in open(os.path.join(GOLD, "dil_k5_table.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        i, js = line.split(":")
+        table[int(i)] = [int(v) for v in js.split()]
+    m = W.hex_mesh(np.arange(6.0), [0.0, 1.0], [0.0, 1.0])    # 5 cubes in a row, all within rc = 10
+    D = oracle.dil(m, 10.0, 0.0)
+    got = {i: [] for i in range(5)}
+    for c, d, *_ in D:
+        got[int(c)].append(int(d))
+    assert got == table
+
+
+def test_dil_contains_every_interacting_pair(oracle):
+    # every molecule pair in range lies in the same cell or in a DIL cell pair (coverage)
+    wl = W.small_random(n_mesh=(4, 4, 4), L=(8.0, 8.0, 8.0), N=180, seed=21)
+    D = oracle.dil(wl.mesh, wl.rcut, 1e-6 * wl.rcut)
+    cells = oracle.locate(wl.mesh, wl.x)
+    P = oracle.pairs(wl.x, wl.rcut, wl.mesh.periodic)
+    keys = set(map(tuple, D.tolist()))
+    for a, b, n0, n1, n2 in P:
+        ca, cb = int(cells[a]), int(cells[b])
+        n = (int(n0), int(n1), int(n2))
+        if ca == cb and n == (0, 0, 0):
+            continue
+        # pair d = x_a - x_b - n.L ; cell pair (ca, cb, n) or its mirror (cb, ca, -n)
+        k1 = (ca, cb, *n)
+        k2 = (cb, ca, *(-v for v in n))
+        assert k1 in keys or k2 in keys
+
+
+# ---------------------------------------------------------------- adjoint pins (P10)
+
+
+def _adj_case():
+    wl = W.small_random(N=120, seed=31, species_frac=0.7)
+    G = W.qround(np.random.default_rng(32).standard_normal((wl.n, 3)))
+    return wl, G
+
+
+def test_adjoint_parameter_fd(oracle):
+    wl, G = _adj_case()
+    gam = 0.1
+    gx, ge, gs, L = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
+    L0 = oracle.loss(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
+    assert abs(L - L0) < 1e-12 * abs(L0)
+    h = 1e-6
+    for which, grad in (("eps", ge), ("sigma", gs)):
+        for p in range(len(wl.eps)):
+            e1, s1 = wl.eps.copy(), wl.sigma.copy()
+            e2, s2 = wl.eps.copy(), wl.sigma.copy()
+            if which == "eps":
+                e1[p] += h; e2[p] -= h
+            else:
+                s1[p] += h; s2[p] -= h
+            fd = (oracle.loss(wl.x, wl.species, e1, s1, wl.rcut, wl.mesh.periodic, G, gam)
+                  - oracle.loss(wl.x, wl.species, e2, s2, wl.rcut, wl.mesh.periodic, G, gam)) / (2 * h)
+            assert abs(fd - grad[p]) < 1e-6 * max(1.0, abs(grad[p])), (which, p, fd, grad[p])
+    # eps-homogeneity: sum_t eps_t dL/deps_t = L
+    assert abs((wl.eps * ge).sum() - L) < 1e-10 * abs(L)
+
+
+def test_adjoint_position_fd_and_invariants(oracle):
+    wl, G = _adj_case()
+    gam = 0.1
+    gx, ge, gs, L = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
+    assert np.abs(gx.sum(axis=0)).max() < 1e-12 * np.abs(gx).sum()
+    h = 1e-6
+    P0 = oracle.pairs(wl.x, wl.rcut, wl.mesh.periodic)
+    rng = np.random.default_rng(33)
+    checked = 0
+    for _ in range(24):
+        a, k = int(rng.integers(wl.n)), int(rng.integers(3))
+        xp, xm = wl.x.copy(), wl.x.copy()
+        xp[a, k] += h
+        xm[a, k] -= h
+        if len(oracle.pairs(xp, wl.rcut, wl.mesh.periodic)) != len(P0) or \
+           len(oracle.pairs(xm, wl.rcut, wl.mesh.periodic)) != len(P0):
+            continue
+        fd = (oracle.loss(xp, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
+              - oracle.loss(xm, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)) / (2 * h)
+        assert abs(fd - gx[a, k]) < 1e-6 * max(1.0, np.sqrt((gx ** 2).mean())), (a, k, fd, gx[a, k])
+        checked += 1
+    assert checked >= 16
+
+
+def test_adjoint_hessian_symmetry(oracle):
+    wl, G = _adj_case()
+    V = W.qround(np.random.default_rng(34).standard_normal((wl.n, 3)))
+    # with gamma = 0 the adjoint is -H G (H the Hessian of U), so <V, adj(G)> = <G, adj(V)>
+    ag = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, 0.0)[0]
+    av = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, V, 0.0)[0]
+    lhs, rhs = float((V * ag).sum()), float((G * av).sum())
+    assert abs(lhs - rhs) < 1e-11 * max(abs(lhs), 1.0)
+    # gamma-only loss is U: adjoint = gamma grad U = -gamma F
+    F = oracle.forces(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic)[0]
+    a0 = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, np.zeros_like(G), 0.5)[0]
+    assert np.allclose(a0, -0.5 * F, rtol=0, atol=1e-13 * np.abs(F).max())
+
+
+# ---------------------------------------------------------------- NVE (P11)
+
+
+def _verlet_energy_span(oracle, x0, lat, dt, steps):
+    x = x0.copy()
+    v = np.zeros_like(x)
+    sp = np.zeros(len(x), np.int32)
+    F, U, _, npairs0 = oracle.forces(x, sp, [1.0], [1.0], 2.5, lat)
+    uc = oracle.lj(6.25)[0]
+    E0 = U - npairs0 * uc
+    span = 0.0
+    for _ in range(steps):
+        v += 0.5 * dt * F
+        x += dt * v
+        F, U, _, npairs = oracle.forces(x, sp, [1.0], [1.0], 2.5, lat)
+        assert npairs == npairs0   # crossing-free system: the pair set never changes
+        v += 0.5 * dt * F
+        E = 0.5 * (v ** 2).sum() + U - npairs * uc
+        span = max(span, abs(E - E0))
+    return span
+
+
+def test_nve_energy_error_scales_dt2(oracle):
+    wl = W.fcc_cube(10.08, 4, 6, jitter=0.02, seed=41)
+    lat = wl.mesh.periodic
+    T = 0.2
+    s1 = _verlet_energy_span(oracle, wl.x, lat, 0.004, int(T / 0.004))
+    s2 = _verlet_energy_span(oracle, wl.x, lat, 0.002, int(T / 0.002))
+    ratio = s1 / s2
+    assert 3.2 < ratio < 4.8, ratio
