@@ -1,0 +1,168 @@
+/*
+ * aica.h - C ABI of the MI355X-native AICA Lennard-Jones pair-force library.
+ *
+ * The Arbitrary Interacting Cells Algorithm (Macpherson & Reese, arXiv
+ * cs/0702131) evaluates short-range pair forces for molecules held in the
+ * cells of a static, unstructured, arbitrary polyhedral mesh (Sec. 2.2, 2.3).
+ * Each cell interacts with itself and with the cells on its direct
+ * interaction list (DIL), every cell pair being listed once (Sec. 2.2,
+ * App. A.1); periodic boundaries are handled by referred cells, i.e.
+ * translated images of real cells (Sec. 2.1, 2.2.1, 2.2.2).  On one GPU only
+ * periodic referral exists, so every referring transform is a lattice
+ * translation (R = I in the referring-result equation of Sec. 2.2.2).
+ *
+ * Conventions for every call:
+ *   - Return value: AICA_OK (0) or a negative AICA_E_* code; nothing throws.
+ *     aica_last_error() gives a message for the calling thread.
+ *   - "host" pointers are CPU memory; "device" pointers are HIP device memory
+ *     (e.g. torch tensor data pointers).  The caller owns all arrays; the
+ *     library owns the aica_dil handle and everything inside it.
+ *   - Device work is stream-ordered on the caller's HIP stream (hipStream_t
+ *     passed as void*; NULL means the legacy default stream).
+ *   - Molecule ids are 0..n-1 in the caller's order; results come back in the
+ *     caller's order.  Cell ids are the mesh's own cell indices.
+ */
+#ifndef AICA_H
+#define AICA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AICA_OK 0
+#define AICA_E_INVAL -1      /* bad argument: null pointer, size, dtype, NaN position, wrong call order */
+#define AICA_E_MESH -2       /* invalid mesh: bad indices, open or inverted cell (non-positive tetrahedron) */
+#define AICA_E_RCUT -3       /* rcut + guard >= half a periodic length (minimum image would not hold) */
+#define AICA_E_UNLOCATED -4  /* some molecule lies in no cell of the mesh */
+#define AICA_E_NOMEM -5      /* host or device allocation failed */
+#define AICA_E_HIP -6        /* a HIP runtime call failed */
+
+#define AICA_FP32 1
+#define AICA_FP64 2
+
+/* Static unstructured polyhedral mesh (Sec. 2.3: a cell's index implies
+ * nothing about its location or connectivity).  Host memory, read during
+ * aica_build_dil only and not retained. */
+typedef struct aica_mesh {
+  int64_t n_points;
+  const double *points;      /* [n_points][3] */
+  int64_t n_faces;
+  const int64_t *face_off;   /* [n_faces+1]: face f uses face_pts[face_off[f] .. face_off[f+1]) */
+  const int32_t *face_pts;   /* vertex loops; right-hand normal points out of the owner cell */
+  const int32_t *owner;      /* [n_faces] owning cell */
+  const int32_t *neighbour;  /* [n_faces] other cell, or -1 on a boundary face */
+  int64_t n_cells;
+  int32_t n_periodic;        /* number of periodic directions (0..3) */
+  double periodic_vec[3][3]; /* mutually orthogonal lattice translations of the periodic directions */
+} aica_mesh;
+
+/* Lennard-Jones model and evaluation options.  Host memory. */
+typedef struct aica_params {
+  double rcut;               /* cut-off radius, absolute, the same for every species pair; <= the DIL's rcut */
+  int32_t n_species;         /* 1..8 */
+  const double *eps;         /* [n_species] per-species epsilon (Lorentz-Berthelot: eps_ab = sqrt(eps_a eps_b)) */
+  const double *sigma;       /* [n_species] per-species sigma (sigma_ab = (sigma_a + sigma_b)/2) */
+  int32_t precision;         /* AICA_FP32: FP32 pair arithmetic, compensated FP32 force sums, FP64 energy and
+                                virial; AICA_FP64: FP64 throughout */
+  int32_t compensated;       /* FP32 only: 1 = TwoSum-compensated per-molecule force sums, 0 = plain FP32 */
+} aica_params;
+
+typedef struct aica_dil aica_dil;  /* opaque handle */
+
+/* Setup (Sec. 2.3 and App. A): validate the mesh, build every cell's direct
+ * interaction list and the periodic referred-cell pairs, once.  A cell pair
+ * (c, d, t), t a lattice translation with components in {-1,0,1}, is listed
+ * when the closest distance between cell c and cell d translated by t is
+ * below rcut + guard; each pair is listed once (App. A.1), and no cell is
+ * listed with itself at t = 0.  Cell geometry: each face is fanned into
+ * triangles around the mean of its vertices; the cell is the union of the
+ * tetrahedra (cell vertex mean, face triangle), all of which must have
+ * positive volume.  rcut > 0 is the largest cut-off of any potential
+ * (App. A); guard >= 0 widens the list (Sec. 2.2 guard distance).
+ * Errors: AICA_E_INVAL, AICA_E_MESH, AICA_E_RCUT, AICA_E_NOMEM, AICA_E_HIP.
+ * On success *out owns device geometry and must be freed with aica_dil_free. */
+int aica_build_dil(const aica_mesh *mesh, double rcut, double guard, aica_dil **out);
+
+/* Per-step binning (Sec. 2.2: the library keeps which cell each molecule is
+ * in).  pos_dev: device [n][3] positions in the caller's order, dtype
+ * AICA_FP64 (double) or AICA_FP32 (float); every position must lie in the
+ * mesh (periodic coordinates already wrapped by the caller).  Locates each
+ * molecule's cell (lowest cell index on a shared face), builds the CSR cell
+ * occupancy and the cell-sorted order (ascending molecule id within a cell),
+ * and the per-step work list.  Results stay in the handle.  Synchronises the
+ * stream once to read the unlocated count.
+ * Errors: AICA_E_INVAL (n < 0, null, bad dtype), AICA_E_UNLOCATED (the
+ * count is in aica_last_error), AICA_E_NOMEM, AICA_E_HIP. */
+int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, void *hip_stream);
+
+/* Per-step forces (Sec. 2.3.1 real-real and 2.3.2 real-referred loops, with
+ * the reaction -F applied to the partner, Sec. 2.2): for every unordered pair
+ * {a, b + image} with |d|^2 < rcut^2, d = x_a - x_b - t,
+ *   u = 4 eps_ab [(sigma_ab/r)^12 - (sigma_ab/r)^6],  F_a += g d, F_b -= g d,
+ *   g = 24 eps_ab [2 sigma_ab^12 r^-14 - sigma_ab^6 r^-8],
+ *   U = sum u, W = sum g |d|^2 (virial sum r.F), npairs = number of pairs.
+ * pos_dev must be the array last passed to aica_bin (same pointer, dtype and
+ * n; otherwise AICA_E_INVAL).  species_dev: device int32 [n] in 0..n_species-1,
+ * or NULL for all-zero.  forces_dev: device [n][3] in the compute precision's
+ * dtype (float for AICA_FP32, double for AICA_FP64), caller order, overwritten.
+ * uw_dev: device double[2] = {U, W}, overwritten; npairs_dev: device int64,
+ * overwritten.  Either may be NULL.  Results are deterministic (fixed
+ * summation order, no atomics on forces).  Errors: AICA_E_INVAL, AICA_E_NOMEM,
+ * AICA_E_HIP. */
+int aica_forces(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
+                void *forces_dev, double *uw_dev, int64_t *npairs_dev, void *hip_stream);
+
+/* Adjoint of the force evaluation for L = sum_a G_a . F_a + gamma U (the
+ * upstream gradient G on the forces and gamma on the energy).  Recomputes
+ * every pair term (nothing is stored between the calls):
+ *   dL/dx_a, dL/deps_s, dL/dsigma_s (per species, through Lorentz-Berthelot).
+ * grad_forces_dev: device [n][3] in the compute dtype (G), caller order.
+ * grad_energy: gamma (host scalar).  grad_pos_dev: device [n][3] compute dtype,
+ * overwritten.  grad_eps_dev, grad_sigma_dev: device double[n_species],
+ * overwritten (either may be NULL).  Same preconditions as aica_forces.
+ * Errors: AICA_E_INVAL, AICA_E_NOMEM, AICA_E_HIP. */
+int aica_forces_adjoint(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
+                        const void *grad_forces_dev, double grad_energy, void *grad_pos_dev, double *grad_eps_dev,
+                        double *grad_sigma_dev, void *hip_stream);
+
+/* ---- diagnostics (tests and benchmarks) ---- */
+
+/* The interacting cell pairs in mesh cell ids: (c, d, img) with c < d, or
+ * c == d and img lexicographically positive; img[3] holds the multiples of
+ * the periodic vectors.  Host arrays.  With c == NULL only *n is set. */
+int aica_dil_export(const aica_dil *dil, int64_t *n, int32_t *c, int32_t *d, int8_t *img);
+
+/* The molecule pairs the GPU path evaluates inside the cut-off, as (a, b, img)
+ * with a < b and d = x_a - x_b - sum_k img_k v_k.  Runs the same traversal as
+ * aica_forces after aica_bin.  Host output arrays of capacity cap; *n gets the
+ * count (which may exceed cap: call again with a larger cap). */
+int aica_pairs_export(aica_dil *dil, const void *pos_dev, const aica_params *params, int64_t cap, int64_t *n,
+                      int32_t *a, int32_t *b, int8_t *img, void *hip_stream);
+
+/* Binning of the last aica_bin, host arrays: cell_of[n] (mesh cell id of each
+ * molecule), order[n] (molecule ids in cell-sorted order), cell_count[n_cells]
+ * (molecules per mesh cell).  Any pointer may be NULL. */
+int aica_bin_export(const aica_dil *dil, int32_t *cell_of, int32_t *order, int64_t *cell_count);
+
+typedef struct aica_info {
+  int64_t n_cells, n_dil, n_groups, n_group_pairs, n_molecules, n_jslots;
+  double mesh_volume, build_seconds, group_seconds;
+  int64_t lane_steps;       /* lane-pair evaluations of the last aica_forces (tile work) */
+} aica_info;
+int aica_dil_info(const aica_dil *dil, aica_info *info);
+
+/* Kernel timing with HIP events on the caller's stream: enable, then read the
+ * accumulated milliseconds and launch count of a named kernel
+ * ("pair_fwd", "pair_adj", "bin", "finalize"), and reset. */
+int aica_profile(aica_dil *dil, int32_t enable);
+int aica_profile_read(aica_dil *dil, const char *kernel, double *ms_total, int64_t *launches, int32_t reset);
+
+const char *aica_last_error(void);
+void aica_dil_free(aica_dil *dil);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AICA_H */

@@ -1,0 +1,1236 @@
+// HIP (gfx950) kernels and the C ABI of the AICA Lennard-Jones library.
+//
+// Per step (aica_bin, then aica_forces / aica_forces_adjoint):
+//   locate -> histogram -> scan -> scatter -> in-cell sort     : CSR cell occupancy (Sec. 2.2)
+//   group ranges, j-slot offsets                               : the per-step work list
+//   gather                                                     : cell-sorted SoA, group-local coordinates
+//   pair kernel                                                : real-real and periodic referred pairs,
+//                                                                Newton reactions (Sec. 2.3.1, 2.3.2, 2.2)
+//   finalize, reduce                                           : per-molecule sums in caller order, U, W
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "aica_internal.h"
+#include "aica_kernels.h"
+
+namespace aica {
+const char *last_error_cstr();
+}
+
+using namespace aica;
+
+#define HIPCHK(x)                                                                                       \
+  do {                                                                                                  \
+    hipError_t _e = (x);                                                                                \
+    if (_e != hipSuccess) return fail(AICA_E_HIP, std::string("HIP error: ") + hipGetErrorString(_e) + \
+                                                      " at " + __FILE__ + ":" + std::to_string(__LINE__)); \
+  } while (0)
+
+namespace {
+
+struct DBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~DBuf() {
+    if (p) (void)hipFree(p);
+  }
+  int ensure(size_t nbytes) {
+    if (nbytes <= bytes && p) return AICA_OK;
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    size_t nb = std::max<size_t>(nbytes, 256);
+    if (hipMalloc(&p, nb) != hipSuccess) {
+      p = nullptr;
+      return fail(AICA_E_NOMEM, "device allocation of " + std::to_string(nb) + " bytes failed");
+    }
+    bytes = nb;
+    return AICA_OK;
+  }
+  template <class T>
+  T *as() const {
+    return (T *)p;
+  }
+};
+
+template <class T>
+int upload(DBuf &b, const std::vector<T> &v) {
+  int rc = b.ensure(sizeof(T) * std::max<size_t>(v.size(), 1));
+  if (rc) return rc;
+  if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return AICA_OK;
+}
+
+struct Timer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  double ms = 0;
+  int64_t launches = 0;
+};
+
+}  // namespace
+
+struct aica_dil {
+  Geometry geo;
+  std::vector<int32_t> order, rank;
+  std::vector<CellPair> pairs;
+  double rcut = 0, guard = 0, build_seconds = 0, group_seconds = 0;
+  int device = 0;
+  bool geometry_on_device = false;
+  // device geometry for point location (mesh cell ids)
+  DBuf d_pts, d_foff, d_fpts, d_fcen, d_cf_off, d_cf, d_cf_sgn, d_ccen, d_bb, d_rank;
+  DBuf d_gb_off, d_gb_cell;
+  double glo[3] = {0, 0, 0}, gh = 1;
+  int64_t gnb[3] = {1, 1, 1};
+  // interaction groups (depend on the number density; built on the first aica_bin)
+  bool groups_ready = false;
+  int64_t groups_for_n = -1;
+  Groups grp;
+  DBuf d_orig, d_g_cell0, d_e_off, d_e_B, d_e_vec32, d_e_vec64, d_r_off, d_r_e;
+  // per step
+  bool bin_valid = false;
+  int64_t n = 0;
+  const void *bin_pos = nullptr;
+  int32_t bin_dtype = 0;
+  int64_t jtotal = 0;
+  DBuf d_cell_of, d_count, d_cell_start, d_fill, d_perm, d_g_start, d_mol_group, d_jcnt, d_jb_off;
+  DBuf d_scan_tmp, d_status;
+  // force / adjoint workspace
+  DBuf d_pos, d_own, d_jpart, d_gpart, d_gnp, d_gG, d_gpar;
+  DBuf d_pairs, d_pcount;
+  bool profiling = false;
+  std::map<std::string, Timer> timers;
+};
+
+// =====================================================================================================
+// kernels: binning
+
+namespace {
+
+__device__ __forceinline__ double orient3(const double *a, const double *b, const double *c, const double *d) {
+  const double u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
+  const double v0 = c[0] - a[0], v1 = c[1] - a[1], v2 = c[2] - a[2];
+  const double w0 = d[0] - a[0], w1 = d[1] - a[1], w2 = d[2] - a[2];
+  return u0 * (v1 * w2 - v2 * w1) + u1 * (v2 * w0 - v0 * w2) + u2 * (v0 * w1 - v1 * w0);
+}
+
+// Is p inside cell c: some tetrahedron (cell centroid, face centroid, edge) contains p, with a
+// relative tolerance of 1e-12 of that tetrahedron's volume.
+__device__ bool point_in_cell(const double *p, int32_t c, const double *pts, const int64_t *foff,
+                              const int32_t *fpts, const double *fcen, const int64_t *cf_off, const int32_t *cf,
+                              const int8_t *cf_sgn, const double *ccen) {
+  const double cc[3] = {ccen[3 * (int64_t)c], ccen[3 * (int64_t)c + 1], ccen[3 * (int64_t)c + 2]};
+  for (int64_t k = cf_off[c]; k < cf_off[c + 1]; ++k) {
+    const int32_t f = cf[k];
+    const double fc[3] = {fcen[3 * (int64_t)f], fcen[3 * (int64_t)f + 1], fcen[3 * (int64_t)f + 2]};
+    const int64_t b0 = foff[f], len = foff[f + 1] - b0;
+    for (int64_t j = 0; j < len; ++j) {
+      int64_t ia = fpts[b0 + j], ib = fpts[b0 + (j + 1 == len ? 0 : j + 1)];
+      if (cf_sgn[k] < 0) {
+        int64_t t = ia;
+        ia = ib;
+        ib = t;
+      }
+      const double *a = pts + 3 * ia, *b = pts + 3 * ib;
+      const double v = orient3(cc, fc, a, b);
+      const double tol = -1e-12 * fabs(v);
+      if (orient3(p, fc, a, b) >= tol && orient3(cc, p, a, b) >= tol && orient3(cc, fc, p, b) >= tol &&
+          orient3(cc, fc, a, p) >= tol)
+        return true;
+    }
+  }
+  return false;
+}
+
+template <typename PT>
+__global__ void k_locate(const PT *__restrict__ pos, int64_t n, const double *pts, const int64_t *foff,
+                         const int32_t *fpts, const double *fcen, const int64_t *cf_off, const int32_t *cf,
+                         const int8_t *cf_sgn, const double *ccen, const double *bb, const int32_t *rank,
+                         const int64_t *gb_off, const int32_t *gb_cell, double glo0, double glo1, double glo2,
+                         double gh, int64_t nb0, int64_t nb1, int64_t nb2, int32_t *cell_sorted,
+                         int32_t *count, unsigned long long *status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
+  int32_t found = -1;
+  if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
+    const double f0 = floor((p[0] - glo0) / gh), f1 = floor((p[1] - glo1) / gh), f2 = floor((p[2] - glo2) / gh);
+    if (f0 >= 0 && f1 >= 0 && f2 >= 0 && f0 < (double)nb0 && f1 < (double)nb1 && f2 < (double)nb2) {
+      const int64_t b = (int64_t)f0 + nb0 * ((int64_t)f1 + nb1 * (int64_t)f2);
+      for (int64_t k = gb_off[b]; k < gb_off[b + 1]; ++k) {
+        const int32_t c = gb_cell[k];
+        const double *B = bb + 6 * (int64_t)c;
+        if (p[0] < B[0] || p[1] < B[1] || p[2] < B[2] || p[0] > B[3] || p[1] > B[4] || p[2] > B[5]) continue;
+        if (point_in_cell(p, c, pts, foff, fpts, fcen, cf_off, cf, cf_sgn, ccen)) {
+          found = c;
+          break;
+        }
+      }
+    }
+  }
+  if (found < 0) {
+    cell_sorted[i] = -1;
+    atomicAdd(status, 1ull);
+  } else {
+    const int32_t s = rank[found];
+    cell_sorted[i] = s;
+    atomicAdd(&count[s], 1);
+  }
+}
+
+// ---- exclusive scan of int32 counts into OutT offsets (out[n] = total)
+
+constexpr int kScanThreads = 1024, kScanItems = 4, kScanTile = kScanThreads * kScanItems;
+
+template <typename OutT>
+__device__ OutT block_exclusive_scan(OutT v, OutT *sh, OutT &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  OutT x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    OutT y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    OutT s = lane < (kScanThreads / 64) ? sh[lane] : 0;
+    OutT t = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      OutT y = __shfl_up(t, o, 64);
+      if (lane >= o) t += y;
+    }
+    if (lane < kScanThreads / 64) sh[lane] = t - s;
+    if (lane == kScanThreads / 64 - 1) sh[kScanThreads / 64] = t;
+  }
+  __syncthreads();
+  total = sh[kScanThreads / 64];
+  OutT r = x - v + sh[w];
+  __syncthreads();
+  return r;
+}
+
+template <typename InT, typename OutT>
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const InT *in, int64_t n, OutT *out, OutT *tile_sum) {
+  __shared__ OutT sh[kScanThreads / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  OutT v[kScanItems], s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? (OutT)in[base + k] : 0;
+    s += v[k];
+  }
+  OutT total;
+  OutT ex = block_exclusive_scan<OutT>(s, sh, total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = ex;
+    ex += v[k];
+  }
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+template <typename OutT>
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(OutT *tile_sum, int64_t ntiles, OutT *out, int64_t n) {
+  __shared__ OutT sh[kScanThreads / 64 + 1];
+  OutT carry = 0;
+  for (int64_t b = 0; b < ntiles; b += kScanThreads) {
+    const int64_t i = b + threadIdx.x;
+    OutT v = i < ntiles ? tile_sum[i] : 0, total;
+    OutT ex = block_exclusive_scan<OutT>(v, sh, total);
+    if (i < ntiles) tile_sum[i] = ex + carry;
+    carry += total;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+template <typename OutT>
+__global__ void k_scan_add(OutT *out, int64_t n, const OutT *tile_sum) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += tile_sum[i / kScanTile];
+}
+
+__global__ void k_scatter(const int32_t *cell_sorted, int64_t n, const int32_t *cell_start, int32_t *fill,
+                          int32_t *perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t c = cell_sorted[i];
+  const int32_t slot = cell_start[c] + atomicAdd(&fill[c], 1);
+  perm[slot] = (int32_t)i;
+}
+
+// Ascending molecule id inside every cell (the scatter's atomics leave an arbitrary order).
+__global__ void k_sort_cells(const int32_t *cell_start, int64_t nc, int32_t *perm) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const int32_t b = cell_start[c], e = cell_start[c + 1];
+  for (int32_t i = b + 1; i < e; ++i) {
+    const int32_t v = perm[i];
+    int32_t j = i - 1;
+    while (j >= b && perm[j] > v) {
+      perm[j + 1] = perm[j];
+      --j;
+    }
+    perm[j + 1] = v;
+  }
+}
+
+__global__ void k_group_ranges(const int32_t *cell_start, const int32_t *g_cell0, int64_t ng, int32_t *g_start,
+                               int32_t *mol_group) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a > ng) return;
+  const int32_t s = cell_start[g_cell0[a]];
+  g_start[a] = s;
+  if (a < ng) {
+    const int32_t e = cell_start[g_cell0[a + 1]];
+    for (int32_t m = s; m < e; ++m) mol_group[m] = (int32_t)a;
+  }
+}
+
+__global__ void k_entry_counts(const int32_t *e_B, int64_t E, const int32_t *g_start, int32_t *cnt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int32_t B = e_B[e];
+  cnt[e] = g_start[B + 1] - g_start[B];
+}
+
+template <typename T>
+__global__ void k_fill(T *p, int64_t n, T v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// =====================================================================================================
+// kernels: forces
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = float4;
+};
+template <>
+struct Vec4<double> {
+  using type = double4;
+};
+
+// Gather positions into cell-sorted order, in group-local coordinates (x - origin of the molecule's
+// group); the species id rides in .w as integer bits.
+template <typename T, typename PT>
+__global__ void k_gather(const PT *__restrict__ pos, const int32_t *__restrict__ species, const int32_t *perm,
+                         const int32_t *mol_group, const double *orig, int64_t n, int nsp,
+                         typename Vec4<T>::type *out) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  const int32_t id = perm[m];
+  const int32_t a = mol_group[m];
+  typename Vec4<T>::type v;
+  v.x = (T)((double)pos[3 * (int64_t)id] - orig[3 * (int64_t)a]);
+  v.y = (T)((double)pos[3 * (int64_t)id + 1] - orig[3 * (int64_t)a + 1]);
+  v.z = (T)((double)pos[3 * (int64_t)id + 2] - orig[3 * (int64_t)a + 2]);
+  const int32_t t = species ? min(max(species[id], 0), nsp - 1) : 0;  // out-of-range ids are clamped
+  if constexpr (sizeof(T) == 4)
+    v.w = __builtin_bit_cast(float, t);
+  else
+    v.w = __builtin_bit_cast(double, (int64_t)t);
+  out[m] = v;
+}
+
+struct LJTab {
+  float sig2[64], e24[64], e4[64];
+  double sig2d[64], e24d[64], e4d[64];
+  float rc2, band;
+  double rc2d;
+  int nsp;
+};
+
+template <typename T>
+__device__ __forceinline__ int type_of(T w) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(int, w);
+  else
+    return (int)__builtin_bit_cast(int64_t, w);
+}
+
+template <typename T>
+__device__ __forceinline__ T tab_sig2(const LJTab &t, int k) {
+  if constexpr (sizeof(T) == 4) return t.sig2[k]; else return t.sig2d[k];
+}
+template <typename T>
+__device__ __forceinline__ T tab_e24(const LJTab &t, int k) {
+  if constexpr (sizeof(T) == 4) return t.e24[k]; else return t.e24d[k];
+}
+template <typename T>
+__device__ __forceinline__ T tab_e4(const LJTab &t, int k) {
+  if constexpr (sizeof(T) == 4) return t.e4[k]; else return t.e4d[k];
+}
+
+// Per-lane Lennard-Jones parameters of the lane's i-species against j-species 0 and 1 (MIX <= 1),
+// or the full table (MIX == 2: looked up per pair).
+template <typename T, int MIX>
+struct LaneLJ {
+  T s0, s1, g0, g1, u0, u1;
+  int ti;
+  __device__ __forceinline__ void init(const LJTab &t, int ti_) {
+    ti = ti_;
+    s0 = tab_sig2<T>(t, ti * 8);
+    g0 = tab_e24<T>(t, ti * 8);
+    u0 = tab_e4<T>(t, ti * 8);
+    if (MIX >= 1) {
+      s1 = tab_sig2<T>(t, ti * 8 + 1);
+      g1 = tab_e24<T>(t, ti * 8 + 1);
+      u1 = tab_e4<T>(t, ti * 8 + 1);
+    }
+  }
+  __device__ __forceinline__ void get(const LJTab &t, int tj, T &sig2, T &e24, T &e4) const {
+    if (MIX == 0) {
+      sig2 = s0;
+      e24 = g0;
+      e4 = u0;
+    } else if (MIX == 1) {
+      const bool b = tj != 0;
+      sig2 = b ? s1 : s0;
+      e24 = b ? g1 : g0;
+      e4 = b ? u1 : u0;
+    } else {
+      const int k = ti * 8 + tj;
+      sig2 = tab_sig2<T>(t, k);
+      e24 = tab_e24<T>(t, k);
+      e4 = tab_e4<T>(t, k);
+    }
+  }
+};
+
+__device__ __forceinline__ float fast_rcp(float s) { return __builtin_amdgcn_rcpf(s); }
+__device__ __forceinline__ double fast_rcp(double s) { return 1.0 / s; }
+
+// One pair: d = x_i - x_j (image already applied), returns g (force factor), u and whether the pair
+// is inside the cut-off.  The FP32 decision is made exact near r_cut: when |s - rc^2| is within the
+// FP32 rounding band, s is recomputed in FP64 from the exact FP32 differences.
+template <typename T>
+__device__ __forceinline__ void lj_pair(T dx, T dy, T dz, T sig2, T e24, T e4, const LJTab &tab, bool extra, T &g,
+                                        T &u, T &s_out, bool &in) {
+  T s;
+  if constexpr (sizeof(T) == 4) {
+    s = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    bool inn = s < tab.rc2;
+    if (fabsf(s - tab.rc2) <= tab.band) {
+      const double sd = (double)dx * (double)dx + (double)dy * (double)dy + (double)dz * (double)dz;
+      inn = sd < tab.rc2d;
+    }
+    in = inn && extra;
+  } else {
+    s = fma(dx, dx, fma(dy, dy, dz * dz));
+    in = (s < tab.rc2d) && extra;
+  }
+  const T inv = fast_rcp(s);
+  const T sr2 = sig2 * inv;
+  const T sr6 = sr2 * sr2 * sr2;
+  const T gg = e24 * inv * sr6 * (sr6 + sr6 - (T)1);
+  const T uu = e4 * sr6 * (sr6 - (T)1);
+  g = in ? gg : (T)0;
+  u = in ? uu : (T)0;
+  s_out = s;
+}
+
+template <typename T>
+__device__ __forceinline__ T far_i() { return (T)1e15; }
+template <typename T>
+__device__ __forceinline__ T far_j() { return (T)-1e15; }
+
+// MODE 0: forces, energy, virial.  MODE 1: export the pair list.
+//
+// One wave per interaction group A.  The wave's four 16-lane rows hold the same i-chunk (16
+// molecules of A, one per lane) and work through A's group-pair entries round-robin; for each
+// entry (B, image) the row stages 16 j-molecules of B in LDS and runs a 16-step rotation: at step s
+// lane c pairs i_c with j_{(c+s) mod 16}.  F_i stays in the lane; the reaction -F goes into a
+// per-row accumulator that rotates one lane per step (DPP row_ror) so that after the tile lane c
+// holds the total reaction on j_c, which is stored (no atomics) into the entry's j-slot buffer.
+// The self entry (A, A, 0) uses half tiles so each unordered pair inside A is evaluated once.
+template <typename T, int MIX, int MODE, bool COMP>
+__global__ __launch_bounds__(kBlock) void k_pair_fwd(
+    const typename Vec4<T>::type *__restrict__ pos, const int32_t *__restrict__ g_start,
+    const int64_t *__restrict__ e_off, const int32_t *__restrict__ e_B, const typename Vec4<T>::type *__restrict__ e_vec,
+    const int64_t *__restrict__ jb_off, T *__restrict__ jpart, int64_t J, T *__restrict__ own, int64_t N,
+    double *__restrict__ gpart, unsigned long long *__restrict__ gnp, int64_t ng, int64_t nblocks_padded, LJTab tab,
+    const int32_t *__restrict__ perm, int64_t cap, int32_t *__restrict__ pairs_out,
+    unsigned long long *__restrict__ pair_count) {
+  using V4 = typename Vec4<T>::type;
+  __shared__ V4 lds[kWavesPerBlock][64];
+  const int lane = threadIdx.x & 63, row = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
+  const int64_t a = xcd_block(blockIdx.x, nblocks_padded) * kWavesPerBlock + w;
+  if (a >= ng) return;
+  V4 *my = &lds[w][row * kRow];
+  const int32_t m0 = g_start[a], nA = g_start[a + 1] - m0;
+  const int64_t e0 = e_off[a], e1 = e_off[a + 1];
+  double Ul = 0, Wl = 0;
+  unsigned npl = 0;
+  for (int ib = 0; ib < nA; ib += kRow) {
+    const int ni = min(kRow, nA - ib);
+    V4 pi;
+    if (c < ni) {
+      pi = pos[m0 + ib + c];
+    } else {
+      pi.x = pi.y = pi.z = far_i<T>();
+      pi.w = (T)0;
+    }
+    LaneLJ<T, MIX> lp;
+    lp.init(tab, c < ni ? type_of<T>(pi.w) : 0);
+    T fx = 0, fy = 0, fz = 0, cx = 0, cy = 0, cz = 0;
+    for (int64_t e = e0 + row; e < e1; e += 4) {
+      const int32_t B = e_B[e];
+      const V4 ov = e_vec[e];
+      const int32_t mb0 = g_start[B], nB = g_start[B + 1] - mb0;
+      const bool self = (e == e0);
+      const T xi = pi.x - ov.x, yi = pi.y - ov.y, zi = pi.z - ov.z;
+      const int64_t jo = jb_off[e];
+      for (int jb = self ? ib : 0; jb < nB; jb += kRow) {
+        const int nj = min(kRow, nB - jb);
+        V4 pj;
+        if (c < nj) {
+          pj = pos[mb0 + jb + c];
+        } else {
+          pj.x = pj.y = pj.z = far_j<T>();
+          pj.w = (T)0;
+        }
+        my[c] = pj;
+        wave_lds_sync();
+        T tfx = 0, tfy = 0, tfz = 0, ax = 0, ay = 0, az = 0, tu = 0, tw = 0;
+        const bool half = self && (jb == ib);
+        auto step = [&](int s, bool extra) {
+          const int slot = (c + s) & 15;
+          const V4 q = my[slot];
+          const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+          T sig2, e24, e4;
+          lp.get(tab, type_of<T>(q.w), sig2, e24, e4);
+          T g, u, s2;
+          bool in;
+          lj_pair<T>(dx, dy, dz, sig2, e24, e4, tab, extra, g, u, s2, in);
+          if (MODE == 0) {
+            const T gx = g * dx, gy = g * dy, gz = g * dz;
+            tfx += gx;
+            tfy += gy;
+            tfz += gz;
+            ax = ror15(ax) - gx;
+            ay = ror15(ay) - gy;
+            az = ror15(az) - gz;
+            tu += u;
+            tw += g * s2;
+            npl += in ? 1u : 0u;
+          } else {
+            if (in) {
+              const unsigned long long k = atomicAdd(pair_count, 1ull);
+              if ((int64_t)k < cap) {
+                pairs_out[3 * k] = perm[m0 + ib + c];
+                pairs_out[3 * k + 1] = perm[mb0 + jb + slot];
+                pairs_out[3 * k + 2] = type_of<T>(ov.w);
+              }
+            }
+          }
+        };
+        if (half) {
+#pragma unroll
+          for (int s = 1; s < 8; ++s) step(s, true);
+          step(8, c < 8);
+        } else {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) step(s, true);
+        }
+        if (MODE == 0) {
+          // after the last step s_last lane c holds the reaction on slot (c + s_last) mod 16
+          const int ws = (c + (half ? 8 : 15)) & 15;
+          if (ws < nj) {
+            const int64_t k = jo + jb + ws;
+            if (ib == 0) {
+              jpart[k] = ax;
+              jpart[J + k] = ay;
+              jpart[2 * J + k] = az;
+            } else {
+              jpart[k] += ax;
+              jpart[J + k] += ay;
+              jpart[2 * J + k] += az;
+            }
+          }
+          if (COMP) {
+            T s, err;
+            two_sum(fx, tfx, s, err);
+            fx = s;
+            cx += err;
+            two_sum(fy, tfy, s, err);
+            fy = s;
+            cy += err;
+            two_sum(fz, tfz, s, err);
+            fz = s;
+            cz += err;
+          } else {
+            fx += tfx;
+            fy += tfy;
+            fz += tfz;
+          }
+          Ul += (double)tu;
+          Wl += (double)tw;
+        }
+        wave_lds_sync();
+      }
+    }
+    if (MODE == 0) {
+      // combine the four rows' partial F_i (lanes c, c+16, c+32, c+48)
+#pragma unroll
+      for (int o = 16; o <= 32; o <<= 1) {
+        const T ox = __shfl_xor(fx, o, 64), oy = __shfl_xor(fy, o, 64), oz = __shfl_xor(fz, o, 64);
+        const T pcx = __shfl_xor(cx, o, 64), pcy = __shfl_xor(cy, o, 64), pcz = __shfl_xor(cz, o, 64);
+        if (COMP) {
+          T s, err;
+          two_sum(fx, ox, s, err);
+          fx = s;
+          cx += pcx + err;
+          two_sum(fy, oy, s, err);
+          fy = s;
+          cy += pcy + err;
+          two_sum(fz, oz, s, err);
+          fz = s;
+          cz += pcz + err;
+        } else {
+          fx += ox;
+          fy += oy;
+          fz += oz;
+        }
+      }
+      if (row == 0 && c < ni) {
+        const int64_t m = m0 + ib + c;
+        own[m] = fx;
+        own[N + m] = fy;
+        own[2 * N + m] = fz;
+        own[3 * N + m] = cx;
+        own[4 * N + m] = cy;
+        own[5 * N + m] = cz;
+      }
+    }
+  }
+  if (MODE == 0) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      Ul += __shfl_xor(Ul, o, 64);
+      Wl += __shfl_xor(Wl, o, 64);
+      npl += __shfl_xor(npl, o, 64);
+    }
+    if (lane == 0) {
+      gpart[2 * a] = Ul;
+      gpart[2 * a + 1] = Wl;
+      gnp[a] = npl;
+    }
+  }
+}
+
+// Per-molecule totals: own (hi, lo) plus the j-slot partials of every entry whose j-group holds the
+// molecule, summed in a fixed order (TwoSum-compensated for FP32), written in caller order.
+template <typename T, bool COMP>
+__global__ void k_finalize(const T *__restrict__ own, const T *__restrict__ jpart, int64_t J, int64_t N,
+                           const int32_t *__restrict__ mol_group, const int32_t *__restrict__ g_start,
+                           const int64_t *__restrict__ r_off, const int32_t *__restrict__ r_e,
+                           const int64_t *__restrict__ jb_off, const int32_t *__restrict__ perm, T *__restrict__ out) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const int32_t a = mol_group[m];
+  const int32_t p = (int32_t)(m - g_start[a]);
+  T h[3] = {own[m], own[N + m], own[2 * N + m]};
+  T l[3] = {own[3 * N + m], own[4 * N + m], own[5 * N + m]};
+  for (int64_t r = r_off[a]; r < r_off[a + 1]; ++r) {
+    const int64_t k = jb_off[r_e[r]] + p;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const T v = jpart[q * J + k];
+      if (COMP) {
+        T s, err;
+        two_sum(h[q], v, s, err);
+        h[q] = s;
+        l[q] += err;
+      } else {
+        h[q] += v;
+      }
+    }
+  }
+  const int64_t id = perm[m];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) out[3 * id + q] = h[q] + l[q];
+}
+
+// Fixed-order reduction of per-group partials (deterministic): U, W (FP64) and the pair count.
+__global__ __launch_bounds__(1024) void k_reduce_parts(const double *gpart, const unsigned long long *gnp, int64_t ng,
+                                                       double *uw, int64_t *npairs) {
+  __shared__ double su[1024], sw[1024];
+  __shared__ unsigned long long sn[1024];
+  double u = 0, w = 0;
+  unsigned long long c = 0;
+  for (int64_t i = threadIdx.x; i < ng; i += 1024) {
+    u += gpart[2 * i];
+    w += gpart[2 * i + 1];
+    c += gnp[i];
+  }
+  su[threadIdx.x] = u;
+  sw[threadIdx.x] = w;
+  sn[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      su[threadIdx.x] += su[threadIdx.x + o];
+      sw[threadIdx.x] += sw[threadIdx.x + o];
+      sn[threadIdx.x] += sn[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (uw) {
+      uw[0] = su[0];
+      uw[1] = sw[0];
+    }
+    if (npairs) npairs[0] = (int64_t)sn[0];
+  }
+}
+
+inline unsigned grid1d(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
+
+template <typename OutT>
+int scan_exclusive(aica_dil *h, const int32_t *in, int64_t n, OutT *out, hipStream_t st) {
+  const int64_t ntiles = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
+  int rc = h->d_scan_tmp.ensure(sizeof(OutT) * (ntiles + 1));
+  if (rc) return rc;
+  OutT *ts = h->d_scan_tmp.as<OutT>();
+  hipLaunchKernelGGL((k_scan_tiles<int32_t, OutT>), dim3((unsigned)ntiles), dim3(kScanThreads), 0, st, in, n, out, ts);
+  hipLaunchKernelGGL((k_scan_sums<OutT>), dim3(1), dim3(kScanThreads), 0, st, ts, ntiles, out, n);
+  hipLaunchKernelGGL((k_scan_add<OutT>), dim3(grid1d(n, 256)), dim3(256), 0, st, out, n, (const OutT *)ts);
+  HIPCHK(hipGetLastError());
+  return AICA_OK;
+}
+
+struct ProfScope {
+  aica_dil *h;
+  const char *name;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ProfScope(aica_dil *h_, const char *n, hipStream_t s) : h(h_), name(n), st(s) {
+    if (h->profiling) {
+      (void)hipEventCreate(&e0);
+      (void)hipEventCreate(&e1);
+      (void)hipEventRecord(e0, st);
+    }
+  }
+  ~ProfScope() {
+    if (h->profiling && e0) {
+      (void)hipEventRecord(e1, st);
+      h->timers[name].pending.push_back({e0, e1});
+      h->timers[name].launches++;
+    }
+  }
+};
+
+}  // namespace
+
+// =====================================================================================================
+// setup helpers
+
+static int upload_geometry(aica_dil *h) {
+  const Geometry &g = h->geo;
+  int rc;
+  if ((rc = upload(h->d_pts, g.pts))) return rc;
+  if ((rc = upload(h->d_foff, g.foff))) return rc;
+  if ((rc = upload(h->d_fpts, g.fpts))) return rc;
+  if ((rc = upload(h->d_fcen, g.fcen))) return rc;
+  if ((rc = upload(h->d_cf_off, g.cf_off))) return rc;
+  if ((rc = upload(h->d_cf, g.cf))) return rc;
+  if ((rc = upload(h->d_cf_sgn, g.cf_sgn))) return rc;
+  if ((rc = upload(h->d_ccen, g.ccen))) return rc;
+  if ((rc = upload(h->d_rank, h->rank))) return rc;
+  // padded bounding boxes and the point-location grid (cells listed in every bin their box touches,
+  // ascending cell id so the lowest containing cell is found first)
+  std::vector<double> bb(6 * g.nc);
+  for (int64_t c = 0; c < g.nc; ++c)
+    for (int q = 0; q < 3; ++q) {
+      const double ext = g.hi[3 * c + q] - g.lo[3 * c + q];
+      bb[6 * c + q] = g.lo[3 * c + q] - 1e-9 * ext;
+      bb[6 * c + 3 + q] = g.hi[3 * c + q] + 1e-9 * ext;
+    }
+  if ((rc = upload(h->d_bb, bb))) return rc;
+  double gh = std::cbrt(g.total_volume / (double)g.nc);
+  for (int q = 0; q < 3; ++q) gh = std::max(gh, (g.dom_hi[q] - g.dom_lo[q]) / 2048.0);
+  int64_t nb[3];
+  for (int q = 0; q < 3; ++q) {
+    h->glo[q] = g.dom_lo[q] - 1e-9 * (g.dom_hi[q] - g.dom_lo[q]) - 1e-300;
+    nb[q] = std::max<int64_t>(1, (int64_t)std::ceil((g.dom_hi[q] + 1e-9 * (g.dom_hi[q] - g.dom_lo[q]) - h->glo[q]) / gh));
+    h->gnb[q] = nb[q];
+  }
+  h->gh = gh;
+  const int64_t nbins = nb[0] * nb[1] * nb[2];
+  std::vector<int64_t> off(nbins + 1, 0);
+  auto range = [&](int64_t c, int q, int64_t &b0, int64_t &b1) {
+    b0 = (int64_t)std::floor((bb[6 * c + q] - h->glo[q]) / gh);
+    b1 = (int64_t)std::floor((bb[6 * c + 3 + q] - h->glo[q]) / gh);
+    b0 = std::min(std::max<int64_t>(b0, 0), nb[q] - 1);
+    b1 = std::min(std::max<int64_t>(b1, 0), nb[q] - 1);
+  };
+  for (int64_t c = 0; c < g.nc; ++c) {
+    int64_t lo[3], hi[3];
+    for (int q = 0; q < 3; ++q) range(c, q, lo[q], hi[q]);
+    for (int64_t z = lo[2]; z <= hi[2]; ++z)
+      for (int64_t y = lo[1]; y <= hi[1]; ++y)
+        for (int64_t x = lo[0]; x <= hi[0]; ++x) off[x + nb[0] * (y + nb[1] * z) + 1]++;
+  }
+  for (int64_t b = 0; b < nbins; ++b) off[b + 1] += off[b];
+  std::vector<int32_t> cells(off[nbins]);
+  std::vector<int64_t> fill(off.begin(), off.end() - 1);
+  for (int64_t c = 0; c < g.nc; ++c) {
+    int64_t lo[3], hi[3];
+    for (int q = 0; q < 3; ++q) range(c, q, lo[q], hi[q]);
+    for (int64_t z = lo[2]; z <= hi[2]; ++z)
+      for (int64_t y = lo[1]; y <= hi[1]; ++y)
+        for (int64_t x = lo[0]; x <= hi[0]; ++x) cells[fill[x + nb[0] * (y + nb[1] * z)]++] = (int32_t)c;
+  }
+  if ((rc = upload(h->d_gb_off, off))) return rc;
+  if ((rc = upload(h->d_gb_cell, cells))) return rc;
+  return AICA_OK;
+}
+
+static int ensure_groups(aica_dil *h, int64_t n) {
+  if (h->groups_ready && h->groups_for_n == n) return AICA_OK;
+  auto t0 = std::chrono::steady_clock::now();
+  const double density = (double)n / h->geo.total_volume;
+  double target = 13.0;
+  if (const char *e = getenv("AICA_GROUP_TARGET")) target = std::max(1.0, atof(e));
+  int rc = build_groups(h->geo, h->order, h->pairs, density, target, h->grp);
+  if (rc) return rc;
+  const Groups &G = h->grp;
+  const int64_t E = G.e_off[G.ng];
+  std::vector<float4> v32(E);
+  std::vector<double4> v64(E);
+  for (int64_t e = 0; e < E; ++e) {
+    const int64_t B = G.e_B[e];
+    int64_t A = std::upper_bound(G.e_off.begin(), G.e_off.end(), e) - G.e_off.begin() - 1;
+    double o[3];
+    for (int q = 0; q < 3; ++q) {
+      double t = 0;
+      for (int k = 0; k < h->geo.nper; ++k) t += G.e_img[3 * e + k] * h->geo.per[k][q];
+      o[q] = G.orig[3 * B + q] + t - G.orig[3 * A + q];
+    }
+    const int code = 9 * (G.e_img[3 * e] + 1) + 3 * (G.e_img[3 * e + 1] + 1) + (G.e_img[3 * e + 2] + 1);
+    v32[e] = make_float4((float)o[0], (float)o[1], (float)o[2], __builtin_bit_cast(float, code));
+    v64[e] = make_double4(o[0], o[1], o[2], __builtin_bit_cast(double, (int64_t)code));
+  }
+  if ((rc = upload(h->d_g_cell0, G.cell0))) return rc;
+  if ((rc = upload(h->d_e_off, G.e_off))) return rc;
+  if ((rc = upload(h->d_e_B, G.e_B))) return rc;
+  if ((rc = upload(h->d_e_vec32, v32))) return rc;
+  if ((rc = upload(h->d_e_vec64, v64))) return rc;
+  if ((rc = upload(h->d_r_off, G.r_off))) return rc;
+  if ((rc = upload(h->d_r_e, G.r_e))) return rc;
+  if ((rc = upload(h->d_orig, G.orig))) return rc;
+  h->groups_ready = true;
+  h->groups_for_n = n;
+  h->group_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return AICA_OK;
+}
+
+// =====================================================================================================
+// C ABI (every entry point is declared extern "C" in aica.h)
+
+const char *aica_last_error(void) { return last_error_cstr(); }
+
+int aica_build_dil(const aica_mesh *mesh, double rcut, double guard, aica_dil **out) {
+  if (!out) return fail(AICA_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!(rcut > 0) || !std::isfinite(rcut) || !(guard >= 0) || !std::isfinite(guard))
+    return fail(AICA_E_INVAL, "rcut must be > 0 and guard >= 0");
+  auto t0 = std::chrono::steady_clock::now();
+  aica_dil *h = new (std::nothrow) aica_dil();
+  if (!h) return fail(AICA_E_NOMEM, "handle allocation failed");
+  int rc = build_geometry(mesh, h->geo);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  h->rcut = rcut;
+  h->guard = guard;
+  spatial_order(h->geo, h->order, h->rank);
+  rc = build_cell_pairs(h->geo, h->order, h->rank, rcut + guard, h->pairs);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  h->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = h;
+  return AICA_OK;
+}
+
+void aica_dil_free(aica_dil *h) {
+  if (!h) return;
+  for (auto &kv : h->timers)
+    for (auto &ev : kv.second.pending) {
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+  delete h;
+}
+
+int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, void *hip_stream) {
+  if (!h) return fail(AICA_E_INVAL, "handle is NULL");
+  h->bin_valid = false;
+  if (n < 0 || (n > 0 && !pos_dev)) return fail(AICA_E_INVAL, "bad positions");
+  if (n >= (1LL << 31)) return fail(AICA_E_INVAL, "too many molecules for int32 ids");
+  if (pos_dtype != AICA_FP32 && pos_dtype != AICA_FP64) return fail(AICA_E_INVAL, "pos_dtype must be AICA_FP32 or AICA_FP64");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc;
+  if (!h->geometry_on_device) {
+    // the device copy of the geometry is made on first use, so that setup and the interaction
+    // lists can be built and inspected without a GPU
+    if (hipGetDevice(&h->device) != hipSuccess) return fail(AICA_E_HIP, "no HIP device");
+    if ((rc = upload_geometry(h))) return rc;
+    h->geometry_on_device = true;
+  }
+  rc = ensure_groups(h, n);
+  if (rc) return rc;
+  const int64_t nc = h->geo.nc, ng = h->grp.ng, E = h->grp.e_off[ng];
+  if ((rc = h->d_cell_of.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
+  if ((rc = h->d_count.ensure(4 * nc))) return rc;
+  if ((rc = h->d_cell_start.ensure(4 * (nc + 1)))) return rc;
+  if ((rc = h->d_fill.ensure(4 * nc))) return rc;
+  if ((rc = h->d_perm.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
+  if ((rc = h->d_g_start.ensure(4 * (ng + 1)))) return rc;
+  if ((rc = h->d_mol_group.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
+  if ((rc = h->d_jcnt.ensure(4 * std::max<int64_t>(E, 1)))) return rc;
+  if ((rc = h->d_jb_off.ensure(8 * (E + 1)))) return rc;
+  if ((rc = h->d_status.ensure(64))) return rc;
+  ProfScope ps(h, "bin", st);
+  unsigned long long *status = h->d_status.as<unsigned long long>();
+  hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, status, (int64_t)8, 0ull);
+  hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(), nc, 0);
+  hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_fill.as<int32_t>(), nc, 0);
+  if (n > 0) {
+    if (pos_dtype == AICA_FP64)
+      hipLaunchKernelGGL((k_locate<double>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const double *)pos_dev, n,
+                         h->d_pts.as<double>(), h->d_foff.as<int64_t>(), h->d_fpts.as<int32_t>(), h->d_fcen.as<double>(),
+                         h->d_cf_off.as<int64_t>(), h->d_cf.as<int32_t>(), h->d_cf_sgn.as<int8_t>(), h->d_ccen.as<double>(),
+                         h->d_bb.as<double>(), h->d_rank.as<int32_t>(), h->d_gb_off.as<int64_t>(), h->d_gb_cell.as<int32_t>(),
+                         h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1], h->gnb[2],
+                         h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status);
+    else
+      hipLaunchKernelGGL((k_locate<float>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const float *)pos_dev, n,
+                         h->d_pts.as<double>(), h->d_foff.as<int64_t>(), h->d_fpts.as<int32_t>(), h->d_fcen.as<double>(),
+                         h->d_cf_off.as<int64_t>(), h->d_cf.as<int32_t>(), h->d_cf_sgn.as<int8_t>(), h->d_ccen.as<double>(),
+                         h->d_bb.as<double>(), h->d_rank.as<int32_t>(), h->d_gb_off.as<int64_t>(), h->d_gb_cell.as<int32_t>(),
+                         h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1], h->gnb[2],
+                         h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status);
+    HIPCHK(hipGetLastError());
+  }
+  unsigned long long unl = 0;
+  HIPCHK(hipMemcpyAsync(&unl, status, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (unl > 0) return fail(AICA_E_UNLOCATED, std::to_string(unl) + " molecule(s) lie in no mesh cell");
+  if ((rc = scan_exclusive<int32_t>(h, h->d_count.as<int32_t>(), nc, h->d_cell_start.as<int32_t>(), st))) return rc;
+  if (n > 0)
+    hipLaunchKernelGGL(k_scatter, dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_cell_of.as<int32_t>(), n,
+                       h->d_cell_start.as<int32_t>(), h->d_fill.as<int32_t>(), h->d_perm.as<int32_t>());
+  hipLaunchKernelGGL(k_sort_cells, dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_cell_start.as<int32_t>(), nc,
+                     h->d_perm.as<int32_t>());
+  hipLaunchKernelGGL(k_group_ranges, dim3(grid1d(ng + 1, 256)), dim3(256), 0, st, h->d_cell_start.as<int32_t>(),
+                     h->d_g_cell0.as<int32_t>(), ng, h->d_g_start.as<int32_t>(), h->d_mol_group.as<int32_t>());
+  hipLaunchKernelGGL(k_entry_counts, dim3(grid1d(E, 256)), dim3(256), 0, st, h->d_e_B.as<int32_t>(), E,
+                     h->d_g_start.as<int32_t>(), h->d_jcnt.as<int32_t>());
+  HIPCHK(hipGetLastError());
+  if ((rc = scan_exclusive<int64_t>(h, h->d_jcnt.as<int32_t>(), E, h->d_jb_off.as<int64_t>(), st))) return rc;
+  int64_t jt = 0;
+  HIPCHK(hipMemcpyAsync(&jt, h->d_jb_off.as<int64_t>() + E, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  h->jtotal = jt;
+  h->n = n;
+  h->bin_pos = pos_dev;
+  h->bin_dtype = pos_dtype;
+  h->bin_valid = true;
+  return AICA_OK;
+}
+
+static int build_tab(const aica_dil *h, const aica_params *p, LJTab &t) {
+  if (!p) return fail(AICA_E_INVAL, "params is NULL");
+  if (!(p->rcut > 0) || p->rcut > h->rcut * (1 + 1e-15))
+    return fail(AICA_E_INVAL, "params.rcut must be > 0 and not exceed the DIL's rcut");
+  if (p->n_species < 1 || p->n_species > 8 || !p->eps || !p->sigma)
+    return fail(AICA_E_INVAL, "n_species must be 1..8 with eps and sigma given");
+  if (p->precision != AICA_FP32 && p->precision != AICA_FP64) return fail(AICA_E_INVAL, "bad precision");
+  memset(&t, 0, sizeof t);
+  for (int a = 0; a < p->n_species; ++a)
+    if (!(p->eps[a] > 0) || !(p->sigma[a] > 0)) return fail(AICA_E_INVAL, "eps and sigma must be positive");
+  for (int a = 0; a < p->n_species; ++a)
+    for (int b = 0; b < p->n_species; ++b) {
+      const double e = a == b ? p->eps[a] : std::sqrt(p->eps[a] * p->eps[b]);
+      const double s = a == b ? p->sigma[a] : 0.5 * (p->sigma[a] + p->sigma[b]);
+      const int k = a * 8 + b;
+      t.sig2d[k] = s * s;
+      t.e24d[k] = 24.0 * e;
+      t.e4d[k] = 4.0 * e;
+      t.sig2[k] = (float)(s * s);
+      t.e24[k] = (float)(24.0 * e);
+      t.e4[k] = (float)(4.0 * e);
+    }
+  t.rc2d = p->rcut * p->rcut;
+  t.rc2 = (float)t.rc2d;
+  t.band = (float)(t.rc2d * std::ldexp(1.0, -20));
+  t.nsp = p->n_species;
+  return AICA_OK;
+}
+
+template <typename T, int MODE>
+static int launch_pair(aica_dil *h, const LJTab &tab, bool comp, hipStream_t st, int64_t cap,
+                       unsigned long long *pcount) {
+  using V4 = typename Vec4<T>::type;
+  const int64_t ng = h->grp.ng;
+  const int64_t nblocks = (ng + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int64_t padded = ((nblocks + 7) / 8) * 8;
+  const V4 *pos = h->d_pos.as<V4>();
+  const V4 *ev = sizeof(T) == 4 ? (const V4 *)h->d_e_vec32.p : (const V4 *)h->d_e_vec64.p;
+  T *jpart = h->d_jpart.as<T>();
+  T *own = h->d_own.as<T>();
+  double *gpart = h->d_gpart.as<double>();
+  unsigned long long *gnp = h->d_gnp.as<unsigned long long>();
+  int32_t *pairs_out = MODE == 1 ? h->d_pairs.as<int32_t>() : nullptr;
+  const int nsp = tab.nsp;
+#define AICA_LAUNCH(MIX, COMP)                                                                                     \
+  hipLaunchKernelGGL((k_pair_fwd<T, MIX, MODE, COMP>), dim3((unsigned)padded), dim3(kBlock), 0, st, pos,          \
+                     h->d_g_start.as<int32_t>(), h->d_e_off.as<int64_t>(), h->d_e_B.as<int32_t>(), ev,             \
+                     h->d_jb_off.as<int64_t>(), jpart, h->jtotal, own, h->n, gpart, gnp, ng, padded, tab,          \
+                     h->d_perm.as<int32_t>(), cap, pairs_out, pcount)
+  if (MODE == 1) {
+    if (nsp == 1) AICA_LAUNCH(0, false);
+    else if (nsp == 2) AICA_LAUNCH(1, false);
+    else AICA_LAUNCH(2, false);
+  } else if (comp) {
+    if (nsp == 1) AICA_LAUNCH(0, true);
+    else if (nsp == 2) AICA_LAUNCH(1, true);
+    else AICA_LAUNCH(2, true);
+  } else {
+    if (nsp == 1) AICA_LAUNCH(0, false);
+    else if (nsp == 2) AICA_LAUNCH(1, false);
+    else AICA_LAUNCH(2, false);
+  }
+#undef AICA_LAUNCH
+  HIPCHK(hipGetLastError());
+  return AICA_OK;
+}
+
+template <typename T>
+static int gather(aica_dil *h, const void *pos_dev, const int32_t *species, int tab_nsp, hipStream_t st) {
+  using V4 = typename Vec4<T>::type;
+  const int64_t n = h->n;
+  int rc = h->d_pos.ensure(sizeof(V4) * std::max<int64_t>(n, 1));
+  if (rc) return rc;
+  if (n == 0) return AICA_OK;
+  if (h->bin_dtype == AICA_FP64)
+    hipLaunchKernelGGL((k_gather<T, double>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const double *)pos_dev, species,
+                       h->d_perm.as<int32_t>(), h->d_mol_group.as<int32_t>(), h->d_orig.as<double>(), n, tab_nsp, h->d_pos.as<V4>());
+  else
+    hipLaunchKernelGGL((k_gather<T, float>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const float *)pos_dev, species,
+                       h->d_perm.as<int32_t>(), h->d_mol_group.as<int32_t>(), h->d_orig.as<double>(), n, tab_nsp, h->d_pos.as<V4>());
+  HIPCHK(hipGetLastError());
+  return AICA_OK;
+}
+
+static int check_step(aica_dil *h, const void *pos_dev) {
+  if (!h) return fail(AICA_E_INVAL, "handle is NULL");
+  if (!h->bin_valid) return fail(AICA_E_INVAL, "aica_bin must succeed before this call");
+  if (pos_dev != h->bin_pos) return fail(AICA_E_INVAL, "positions differ from the array passed to aica_bin");
+  return AICA_OK;
+}
+
+template <typename T>
+static int forces_impl(aica_dil *h, const void *pos_dev, const int32_t *species, const LJTab &tab, bool comp,
+                       void *forces_dev, double *uw_dev, int64_t *npairs_dev, hipStream_t st) {
+  const int64_t n = h->n, ng = h->grp.ng, J = h->jtotal;
+  int rc;
+  if ((rc = gather<T>(h, pos_dev, species, tab.nsp, st))) return rc;
+  if ((rc = h->d_jpart.ensure(sizeof(T) * 3 * std::max<int64_t>(J, 1)))) return rc;
+  if ((rc = h->d_own.ensure(sizeof(T) * 6 * std::max<int64_t>(n, 1)))) return rc;
+  if ((rc = h->d_gpart.ensure(sizeof(double) * 2 * std::max<int64_t>(ng, 1)))) return rc;
+  if ((rc = h->d_gnp.ensure(8 * std::max<int64_t>(ng, 1)))) return rc;
+  {
+    ProfScope ps(h, "pair_fwd", st);
+    if ((rc = launch_pair<T, 0>(h, tab, comp, st, 0, nullptr))) return rc;
+  }
+  {
+    ProfScope ps(h, "finalize", st);
+    if (n > 0 && forces_dev) {
+      if (comp && sizeof(T) == 4)
+        hipLaunchKernelGGL((k_finalize<T, true>), dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_own.as<T>(),
+                           h->d_jpart.as<T>(), J, n, h->d_mol_group.as<int32_t>(), h->d_g_start.as<int32_t>(),
+                           h->d_r_off.as<int64_t>(), h->d_r_e.as<int32_t>(), h->d_jb_off.as<int64_t>(),
+                           h->d_perm.as<int32_t>(), (T *)forces_dev);
+      else
+        hipLaunchKernelGGL((k_finalize<T, false>), dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_own.as<T>(),
+                           h->d_jpart.as<T>(), J, n, h->d_mol_group.as<int32_t>(), h->d_g_start.as<int32_t>(),
+                           h->d_r_off.as<int64_t>(), h->d_r_e.as<int32_t>(), h->d_jb_off.as<int64_t>(),
+                           h->d_perm.as<int32_t>(), (T *)forces_dev);
+    }
+    if (uw_dev || npairs_dev)
+      hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(1024), 0, st, h->d_gpart.as<double>(),
+                         h->d_gnp.as<unsigned long long>(), ng, uw_dev, npairs_dev);
+    HIPCHK(hipGetLastError());
+  }
+  return AICA_OK;
+}
+
+int aica_forces(aica_dil *h, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
+                void *forces_dev, double *uw_dev, int64_t *npairs_dev, void *hip_stream) {
+  int rc = check_step(h, pos_dev);
+  if (rc) return rc;
+  LJTab tab;
+  if ((rc = build_tab(h, params, tab))) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (params->precision == AICA_FP32)
+    return forces_impl<float>(h, pos_dev, species_dev, tab, params->compensated != 0, forces_dev, uw_dev, npairs_dev, st);
+  return forces_impl<double>(h, pos_dev, species_dev, tab, false, forces_dev, uw_dev, npairs_dev, st);
+}
+
+int aica_pairs_export(aica_dil *h, const void *pos_dev, const aica_params *params, int64_t cap, int64_t *n_out,
+                      int32_t *a, int32_t *b, int8_t *img, void *hip_stream) {
+  int rc = check_step(h, pos_dev);
+  if (rc) return rc;
+  if (!n_out || cap < 0 || (cap > 0 && (!a || !b || !img))) return fail(AICA_E_INVAL, "bad output arrays");
+  LJTab tab;
+  if ((rc = build_tab(h, params, tab))) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if ((rc = h->d_pairs.ensure(12 * std::max<int64_t>(cap, 1)))) return rc;
+  if ((rc = h->d_pcount.ensure(64))) return rc;
+  unsigned long long *pc = h->d_pcount.as<unsigned long long>();
+  hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, pc, (int64_t)1, 0ull);
+  if (params->precision == AICA_FP32) {
+    if ((rc = gather<float>(h, pos_dev, nullptr, 1, st))) return rc;
+    if ((rc = launch_pair<float, 1>(h, tab, false, st, cap, pc))) return rc;
+  } else {
+    if ((rc = gather<double>(h, pos_dev, nullptr, 1, st))) return rc;
+    if ((rc = launch_pair<double, 1>(h, tab, false, st, cap, pc))) return rc;
+  }
+  unsigned long long cnt = 0;
+  HIPCHK(hipMemcpyAsync(&cnt, pc, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *n_out = (int64_t)cnt;
+  const int64_t k = std::min<int64_t>((int64_t)cnt, cap);
+  if (k > 0) {
+    std::vector<int32_t> buf(3 * k);
+    HIPCHK(hipMemcpy(buf.data(), h->d_pairs.p, 12 * k, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < k; ++i) {
+      int32_t x = buf[3 * i], y = buf[3 * i + 1], code = buf[3 * i + 2];
+      int n0 = code / 9 - 1, n1 = (code / 3) % 3 - 1, n2 = code % 3 - 1;
+      // d = x_i - x_j - t with t = image of the entry; report (min id, max id, image of that order)
+      if (x > y) {
+        std::swap(x, y);
+        n0 = -n0;
+        n1 = -n1;
+        n2 = -n2;
+      }
+      a[i] = x;
+      b[i] = y;
+      img[3 * i] = (int8_t)n0;
+      img[3 * i + 1] = (int8_t)n1;
+      img[3 * i + 2] = (int8_t)n2;
+    }
+  }
+  return AICA_OK;
+}
+
+int aica_forces_adjoint(aica_dil *h, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
+                        const void *grad_forces_dev, double grad_energy, void *grad_pos_dev, double *grad_eps_dev,
+                        double *grad_sigma_dev, void *hip_stream);
+
+int aica_dil_export(const aica_dil *h, int64_t *n, int32_t *c, int32_t *d, int8_t *img) {
+  if (!h || !n) return fail(AICA_E_INVAL, "NULL argument");
+  *n = (int64_t)h->pairs.size();
+  if (!c) return AICA_OK;
+  if (!d || !img) return fail(AICA_E_INVAL, "NULL output array");
+  for (size_t i = 0; i < h->pairs.size(); ++i) {
+    const CellPair &p = h->pairs[i];
+    int32_t x = h->order[p.sc], y = h->order[p.sd];
+    int n0 = p.img[0], n1 = p.img[1], n2 = p.img[2];
+    if (x > y) {
+      std::swap(x, y);
+      n0 = -n0;
+      n1 = -n1;
+      n2 = -n2;
+    }
+    c[i] = x;
+    d[i] = y;
+    img[3 * i] = (int8_t)n0;
+    img[3 * i + 1] = (int8_t)n1;
+    img[3 * i + 2] = (int8_t)n2;
+  }
+  return AICA_OK;
+}
+
+int aica_bin_export(const aica_dil *h, int32_t *cell_of, int32_t *order, int64_t *cell_count) {
+  if (!h) return fail(AICA_E_INVAL, "handle is NULL");
+  if (!h->bin_valid) return fail(AICA_E_INVAL, "aica_bin must succeed first");
+  const int64_t n = h->n, nc = h->geo.nc;
+  if (cell_of && n > 0) {
+    std::vector<int32_t> cs(n);
+    HIPCHK(hipMemcpy(cs.data(), h->d_cell_of.p, 4 * n, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) cell_of[i] = h->order[cs[i]];
+  }
+  if (order && n > 0) HIPCHK(hipMemcpy(order, h->d_perm.p, 4 * n, hipMemcpyDeviceToHost));
+  if (cell_count) {
+    std::vector<int32_t> cs(nc + 1);
+    HIPCHK(hipMemcpy(cs.data(), h->d_cell_start.p, 4 * (nc + 1), hipMemcpyDeviceToHost));
+    for (int64_t s = 0; s < nc; ++s) cell_count[h->order[s]] = cs[s + 1] - cs[s];
+  }
+  return AICA_OK;
+}
+
+int aica_dil_info(const aica_dil *h, aica_info *info) {
+  if (!h || !info) return fail(AICA_E_INVAL, "NULL argument");
+  memset(info, 0, sizeof *info);
+  info->n_cells = h->geo.nc;
+  info->n_dil = (int64_t)h->pairs.size();
+  info->n_groups = h->groups_ready ? h->grp.ng : 0;
+  info->n_group_pairs = h->groups_ready ? h->grp.e_off[h->grp.ng] : 0;
+  info->n_molecules = h->n;
+  info->n_jslots = h->jtotal;
+  info->mesh_volume = h->geo.total_volume;
+  info->build_seconds = h->build_seconds;
+  info->group_seconds = h->group_seconds;
+  info->lane_steps = -1;
+  return AICA_OK;
+}
+
+int aica_profile(aica_dil *h, int32_t enable) {
+  if (!h) return fail(AICA_E_INVAL, "handle is NULL");
+  h->profiling = enable != 0;
+  return AICA_OK;
+}
+
+int aica_profile_read(aica_dil *h, const char *kernel, double *ms_total, int64_t *launches, int32_t reset) {
+  if (!h || !kernel) return fail(AICA_E_INVAL, "NULL argument");
+  Timer &t = h->timers[kernel];
+  for (auto &ev : t.pending) {
+    HIPCHK(hipEventSynchronize(ev.second));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ev.first, ev.second));
+    t.ms += ms;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  t.pending.clear();
+  if (ms_total) *ms_total = t.ms;
+  if (launches) *launches = t.launches;
+  if (reset) {
+    t.ms = 0;
+    t.launches = 0;
+  }
+  return AICA_OK;
+}
+
+
+#include "aica_adjoint.inc"

@@ -1,0 +1,78 @@
+// Internal declarations shared by the host setup code and the HIP launchers.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "aica.h"
+
+namespace aica {
+
+// Thread-local error text; every ABI entry point returns a status code.
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+// Number of host worker threads for setup (AICA_THREADS, else OMP_NUM_THREADS, else hardware).
+int host_threads();
+
+// Host copy of the mesh plus derived cell geometry (Sec. 2.3: static mesh).
+struct Geometry {
+  int64_t np = 0, nf = 0, nc = 0;
+  std::vector<double> pts;       // [np][3]
+  std::vector<int64_t> foff;     // [nf+1]
+  std::vector<int32_t> fpts;     // vertex loops
+  std::vector<int32_t> own, nei; // [nf]
+  int nper = 0;
+  double per[3][3] = {{0}};
+  // derived
+  std::vector<double> fcen;      // [nf][3] face vertex mean
+  std::vector<int64_t> cf_off;   // [nc+1] faces of each cell
+  std::vector<int32_t> cf;       // face ids
+  std::vector<int8_t> cf_sgn;    // +1: cell owns the face (loop outward), -1: neighbour (loop reversed)
+  std::vector<double> ccen;      // [nc][3] vertex mean of the cell's distinct vertices
+  std::vector<double> lo, hi;    // [nc][3] bounding boxes
+  std::vector<double> vol;       // [nc] cell volumes (sum of tetrahedra)
+  std::vector<int64_t> cv_off;   // [nc+1] distinct vertices of each cell
+  std::vector<int32_t> cv;
+  double dom_lo[3], dom_hi[3];   // mesh bounding box
+  double max_half_ext[3];        // largest cell half extent per axis
+  double total_volume = 0;
+};
+
+// Validate the mesh and fill the derived geometry.  Returns AICA_OK or an error code.
+int build_geometry(const aica_mesh *m, Geometry &g);
+
+// Spatially coherent cell order (k-d median splits of cell centroids):
+// order[s] = mesh cell at sorted position s; rank[c] = sorted position of mesh cell c.
+void spatial_order(const Geometry &g, std::vector<int32_t> &order, std::vector<int32_t> &rank);
+
+// One interacting cell pair in sorted cell indices: sc < sd, or sc == sd with img > 0 (lexicographic).
+struct CellPair {
+  int32_t sc, sd;
+  int8_t img[3];
+};
+
+// Build the direct interaction lists (App. A.1 with the closest-point predicate and
+// guard of Sec. 2.2) including periodic referred pairs (lattice translations).
+int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const std::vector<int32_t> &rank,
+                     double R, std::vector<CellPair> &out);
+
+// Interaction groups: consecutive sorted cells packed to an expected occupancy target.
+struct Groups {
+  int64_t ng = 0;
+  std::vector<int32_t> cell0;   // [ng+1] first sorted cell of each group
+  std::vector<int32_t> of_cell; // [nc] group of each sorted cell
+  std::vector<double> orig;     // [ng][3] group origin (multiple of 2^-15)
+  // group-pair list (CSR by the i-group A)
+  std::vector<int64_t> e_off;   // [ng+1]
+  std::vector<int32_t> e_B;     // j-group
+  std::vector<int8_t> e_img;    // [E][3] lattice multiples
+  std::vector<int64_t> r_off;   // [ng+1] reverse list: entries whose j-group is B
+  std::vector<int32_t> r_e;     // entry ids
+};
+
+int build_groups(const Geometry &g, const std::vector<int32_t> &order, const std::vector<CellPair> &pairs,
+                 double density, double target, Groups &out);
+
+}  // namespace aica

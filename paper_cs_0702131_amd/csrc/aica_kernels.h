@@ -1,0 +1,56 @@
+// Device-side helpers shared by the HIP kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aica {
+
+constexpr int kRow = 16;        // lanes per rotation row (a DPP row)
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = 64 * kWavesPerBlock;
+
+// Rotations inside a 16-lane DPP row: lane c receives the value of lane (c + 1) & 15 (row_ror:15),
+// or of lane (c + 7) & 15 (row_ror:9).
+__device__ __forceinline__ float ror15(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x12F, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float ror9(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x129, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double ror15(double v) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x12F, 0xF, 0xF, false);
+  p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x12F, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, p);
+}
+__device__ __forceinline__ double ror9(double v) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x129, 0xF, 0xF, false);
+  p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x129, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, p);
+}
+
+// Error-free transformation a + b = s + e (Knuth's TwoSum).
+template <typename T>
+__device__ __forceinline__ void two_sum(T a, T b, T &s, T &e) {
+  s = a + b;
+  T bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
+// logical blocks so that neighbouring groups (which share j-data) meet in the same L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks_padded) {
+  const int64_t per = nblocks_padded >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+// Make LDS writes of this wave visible to its own later LDS reads.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace aica

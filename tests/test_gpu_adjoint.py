@@ -1,0 +1,132 @@
+"""GPU parity of the hand-written adjoint: against the oracle's analytic gradient,
+FP64 central finite differences, torch.autograd.gradcheck, and identities."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_cs_0702131_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_cs_0702131_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_adjoint(A, wl, G, gamma, precision, dil=None):
+    import torch
+    d = dil or A.DIL(wl.mesh, wl.rcut)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    x = torch.tensor(wl.x, dtype=dt, device="cuda")
+    sp = torch.tensor(wl.species, dtype=torch.int32, device="cuda")
+    A.aica_bin(d, x)
+    Gt = torch.tensor(G, dtype=dt, device="cuda")
+    gx, ge, gs = A.aica_forces_adjoint(d, x, Gt, gamma, sp, wl.eps, wl.sigma, precision=precision)
+    F, uw, npairs = A.aica_forces(d, x, sp, wl.eps, wl.sigma, precision=precision)
+    torch.cuda.synchronize()
+    L = float((G * F.double().cpu().numpy()).sum() + gamma * uw[0].item())
+    return gx.double().cpu().numpy(), ge.cpu().numpy(), gs.cpu().numpy(), L
+
+
+def rel_max(a, b):
+    return np.abs(a - b).max() / np.sqrt((b ** 2).mean())
+
+
+def _case(seed=31, N=300, frac=0.7):
+    wl = W.small_random(n_mesh=(4, 3, 4), L=(8.5, 7.5, 9.0), N=N, seed=seed, species_frac=frac)
+    G = W.qround(np.random.default_rng(seed + 1).standard_normal((wl.n, 3)))
+    return wl, G
+
+
+@pytest.mark.parametrize("frac", [None, 0.7])
+def test_adjoint_vs_oracle(A, oracle, frac):
+    wl, G = _case(frac=frac)
+    gam = 0.1
+    rx, re, rs, rL = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        gx, ge, gs, L = gpu_adjoint(A, wl, G, gam, prec)
+        ex = rel_max(gx, rx)
+        ee = np.abs(ge - re).max() / np.abs(re).max()
+        es = np.abs(gs - rs).max() / np.abs(rs).max()
+        _note(f"adjoint {prec} species={len(wl.eps)}: dx {ex:.2e} deps {ee:.2e} dsig {es:.2e}")
+        assert ex < tol and ee < tol and es < tol
+        assert abs(L - rL) < (1e-12 if prec == "fp64" else 1e-5) * abs(rL)
+
+
+def test_adjoint_vs_finite_differences(A, oracle):
+    """FP64 central differences (h = 1e-6) of the oracle's L for the four parameters and for
+    coordinates whose perturbation leaves the pair set unchanged."""
+    wl, G = _case(seed=41, N=200)
+    gam = 0.1
+    h = 1e-6
+    for prec, tol in (("fp64", 1e-6), ("fp32", 1e-5)):
+        gx, ge, gs, _ = gpu_adjoint(A, wl, G, gam, prec)
+        for which, grad in (("eps", ge), ("sigma", gs)):
+            for p in range(len(wl.eps)):
+                e1, s1, e2, s2 = wl.eps.copy(), wl.sigma.copy(), wl.eps.copy(), wl.sigma.copy()
+                (e1 if which == "eps" else s1)[p] += h
+                (e2 if which == "eps" else s2)[p] -= h
+                fd = (oracle.loss(wl.x, wl.species, e1, s1, wl.rcut, wl.mesh.periodic, G, gam)
+                      - oracle.loss(wl.x, wl.species, e2, s2, wl.rcut, wl.mesh.periodic, G, gam)) / (2 * h)
+                _note(f"fd {prec} {which}[{p}] fd={fd:.10e} adj={grad[p]:.10e}")
+                assert abs(fd - grad[p]) <= tol * abs(fd)
+        P0 = len(oracle.pairs(wl.x, wl.rcut, wl.mesh.periodic))
+        rng = np.random.default_rng(43)
+        rms = np.sqrt((gx ** 2).mean())
+        checked = 0
+        for _ in range(40):
+            a, k = int(rng.integers(wl.n)), int(rng.integers(3))
+            xp, xm = wl.x.copy(), wl.x.copy()
+            xp[a, k] += h
+            xm[a, k] -= h
+            if len(oracle.pairs(xp, wl.rcut, wl.mesh.periodic)) != P0 or \
+               len(oracle.pairs(xm, wl.rcut, wl.mesh.periodic)) != P0:
+                continue
+            fd = (oracle.loss(xp, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
+                  - oracle.loss(xm, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)) / (2 * h)
+            assert abs(fd - gx[a, k]) <= max(tol, 1e-6) * max(rms, abs(fd)), (prec, a, k, fd, gx[a, k])
+            checked += 1
+        assert checked >= 20
+
+
+def test_autograd_gradcheck(A):
+    import torch
+    wl = W.small_random(n_mesh=(3, 3, 3), L=(7.0, 7.0, 7.0), N=40, seed=51, species_frac=0.6, min_sep=0.9)
+    d = A.DIL(wl.mesh, wl.rcut)
+    x = torch.tensor(wl.x, dtype=torch.float64, device="cuda", requires_grad=True)
+    eps = torch.tensor(wl.eps, dtype=torch.float64, requires_grad=True)
+    sig = torch.tensor(wl.sigma, dtype=torch.float64, requires_grad=True)
+    sp = torch.tensor(wl.species, dtype=torch.int32, device="cuda")
+
+    def f(x_, e_, s_):
+        F, U = A.AicaLJ.apply(x_, e_, s_, d, sp, "fp64")
+        return F, U
+
+    assert torch.autograd.gradcheck(f, (x, eps, sig), eps=1e-6, atol=1e-5, rtol=1e-4, nondet_tol=0.0)
+
+
+def test_full_size_identities(A):
+    """219,488-molecule binary mixture: translation invariance (sum dL/dx = 0) and eps-homogeneity
+    (sum_s eps_s dL/deps_s = L, since L is linear in every eps_ab and eps_ab is homogeneous of degree
+    one in (eps_a, eps_b))."""
+    wl = W.config4()
+    G = wl.extra["G"]
+    d = A.DIL(wl.mesh, wl.rcut)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+        gx, ge, gs, L = gpu_adjoint(A, wl, G, wl.extra["gamma"], prec, dil=d)
+        _note(f"config4 adjoint {prec}: sum dL/dx {np.abs(gx.sum(0)).max():.3e}, "
+              f"eps-homogeneity {abs((wl.eps * ge).sum() - L) / abs(L):.3e}")
+        assert np.abs(gx.sum(0)).max() < tol * np.abs(gx).sum(0).max()
+        assert abs((wl.eps * ge).sum() - L) < tol * abs(L)

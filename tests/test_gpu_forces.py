@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Error measures: e_F = max_a |dF_a| / rms_a |F_ref,a|; energies |dU|/|U|.
+Bars: FP64 path 1e-12, FP32 path 1e-5; pair sets and pair counts bit-exact."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_cs_0702131_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_cs_0702131_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def eF(F, Fr):
+    rms = np.sqrt((Fr ** 2).sum(1).mean())
+    return np.sqrt(((F - Fr) ** 2).sum(1)).max() / rms
+
+
+def run_gpu(A, wl, precision, species=True, compensated=True, dil=None, pos_dtype=None):
+    import torch
+    d = dil or A.DIL(wl.mesh, wl.rcut)
+    pdt = pos_dtype or (torch.float64 if precision == "fp64" else torch.float32)
+    x = torch.tensor(wl.x, dtype=pdt, device="cuda")
+    sp = torch.tensor(wl.species, dtype=torch.int32, device="cuda") if species else None
+    A.aica_bin(d, x)
+    F, uw, npairs = A.aica_forces(d, x, sp, wl.eps, wl.sigma, precision=precision, compensated=compensated)
+    torch.cuda.synchronize()
+    return d, x, F.double().cpu().numpy(), uw.cpu().numpy(), int(npairs.cpu()[0])
+
+
+def check_case(A, oracle, wl, precision, tolF, tolU, pairs=True):
+    _note(f"case {wl.name} n={wl.n} {precision}")
+    Fr, Ur, Wr, nr = oracle.forces(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic)
+    d, x, F, uw, npairs = run_gpu(A, wl, precision)
+    assert npairs == nr
+    e = eF(F, Fr)
+    assert e < tolF, e
+    assert abs(uw[0] - Ur) <= tolU * abs(Ur)
+    assert abs(uw[1] - Wr) <= tolU * abs(Wr)
+    if pairs:
+        P = A.aica_pairs_export(d, x, precision=precision)
+        Pr = oracle.pairs(wl.x, wl.rcut, wl.mesh.periodic)
+        assert np.array_equal(P, Pr)
+    return e
+
+
+def test_fcc864_fp64(A, oracle):
+    check_case(A, oracle, W.config1(), "fp64", 1e-12, 1e-12)
+
+
+def test_fcc864_fp32(A, oracle):
+    check_case(A, oracle, W.config1(), "fp32", 1e-5, 1e-6)
+
+
+def test_perfect_fcc_lattice_sum(A, oracle):
+    wl = W.config1(jitter=0.0)
+    d, x, F, uw, npairs = run_gpu(A, wl, "fp64")
+    Fr, Ur, Wr, nr = oracle.forces(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic)
+    assert npairs == nr == 23328
+    # positions are rounded to multiples of 2^-15, so the lattice is perfect only to ~1e-5 and the
+    # forces are small but not zero; they must still match the oracle to the FP64 bar
+    assert eF(F, Fr) < 1e-12
+    assert np.abs(F).max() < 1e-2
+    assert abs(uw[0] - Ur) < 1e-12 * abs(Ur)
+
+
+@pytest.mark.parametrize("seed,periodic,species", [(1, (0, 1, 2), None), (2, (0, 2), 0.7), (3, (1,), 0.5),
+                                                   (4, (), None)])
+def test_small_random_both_precisions(A, oracle, seed, periodic, species):
+    wl = W.small_random(n_mesh=(4, 3, 5), L=(8.5, 7.0, 9.0), N=300, periodic_axes=periodic, seed=seed,
+                        species_frac=species)
+    check_case(A, oracle, wl, "fp64", 1e-12, 1e-12)
+    check_case(A, oracle, wl, "fp32", 1e-5, 1e-6)
+
+
+def test_dense_coarse_mesh_many_chunks(A, oracle):
+    # 2x2x2 cells of 4.2 sigma at density ~0.8: ~60 molecules per cell, several 16-lane chunks
+    # per group and a ragged tail in every tile dimension
+    wl = W.small_random(n_mesh=(2, 2, 2), L=(8.4, 8.4, 8.4), N=470, seed=8, min_sep=0.85, species_frac=0.8)
+    check_case(A, oracle, wl, "fp64", 1e-12, 1e-12)
+    check_case(A, oracle, wl, "fp32", 1e-5, 1e-6)
+
+
+def test_edge_cases_tiny(A, oracle):
+    import torch
+    wl = W.small_random(N=2, seed=9, min_sep=0)
+    for n in (0, 1, 2):
+        sub = W.Workload("tiny", wl.mesh, wl.x[:n].copy(), wl.species[:n].copy(), wl.eps, wl.sigma, wl.rcut,
+                         wl.box_lo, wl.box_hi, wl.periodic_axes)
+        d, x, F, uw, npairs = run_gpu(A, sub, "fp64")
+        Fr, Ur, Wr, nr = oracle.forces(sub.x, sub.species, sub.eps, sub.sigma, sub.rcut, sub.mesh.periodic)
+        assert npairs == nr
+        assert F.shape == (n, 3)
+        if n:
+            assert np.allclose(F, Fr, rtol=1e-12, atol=1e-12)
+        assert abs(uw[0] - Ur) <= 1e-12 * max(abs(Ur), 1e-300)
+
+
+def test_mesh_independence(A, oracle):
+    """Same molecules on different meshes (uniform, jittered, finer, tetrahedral): identical pair
+    sets and FP64 forces (the paper's third verification criterion)."""
+    L = float(W.qround(8.0))
+    base = W.small_random(n_mesh=(4, 4, 4), L=(L, L, L), N=260, seed=12, mesh_jitter=0.0)
+    nodes4, nodes8 = W.uniform_nodes(L, 4), W.uniform_nodes(L, 8)
+    meshes = [base.mesh,
+              W.jitter_interior(W.hex_mesh(nodes4, nodes4, nodes4, periodic_axes=(0, 1, 2)), nodes4, nodes4, nodes4,
+                                0.25, np.random.default_rng(3)),
+              W.hex_mesh(nodes8, nodes8, nodes8, periodic_axes=(0, 1, 2), shuffle_seed=9),
+              W.tet_mesh(W.uniform_nodes(L, 3), W.uniform_nodes(L, 3), W.uniform_nodes(L, 3), periodic_axes=(0, 1, 2))]
+    ref = None
+    for m in meshes:
+        wl = W.Workload("meshind", m, base.x, base.species, base.eps, base.sigma, 2.5, base.box_lo, base.box_hi,
+                        (0, 1, 2))
+        d, x, F, uw, npairs = run_gpu(A, wl, "fp64")
+        P = A.aica_pairs_export(d, x, precision="fp64")
+        if ref is None:
+            ref = (F, uw, P)
+            Fr = oracle.forces(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, m.periodic)[0]
+            assert eF(F, Fr) < 1e-12
+        else:
+            assert np.array_equal(P, ref[2])
+            assert eF(F, ref[0]) < 1e-12
+            assert abs(uw[0] - ref[1][0]) < 1e-12 * abs(ref[1][0])
+
+
+def test_binning_against_oracle(A, oracle):
+    import torch
+    wl = W.small_random(n_mesh=(4, 4, 4), L=(8.0, 8.0, 8.0), N=400, seed=14)
+    d = A.DIL(wl.mesh, 2.5)
+    x = torch.tensor(wl.x, device="cuda")
+    A.aica_bin(d, x)
+    cell_of, order, count = A.aica_bin_export(d, wl.n)
+    assert np.array_equal(cell_of, oracle.locate(wl.mesh, wl.x))
+    assert np.array_equal(count, np.bincount(cell_of, minlength=wl.mesh.n_cells))
+    assert np.array_equal(np.sort(order), np.arange(wl.n))
+    # molecules grouped by cell, ascending id inside each cell
+    co = cell_of[order]
+    starts = np.flatnonzero(np.r_[True, co[1:] != co[:-1]])
+    assert len(starts) == len(np.unique(co))
+    for s, e in zip(starts, np.r_[starts[1:], wl.n]):
+        assert np.all(np.diff(order[s:e]) > 0)
+
+
+def test_unlocated_and_call_order_errors(A):
+    import torch
+    wl = W.small_random(N=50, seed=15, periodic_axes=(0, 2))
+    d = A.DIL(wl.mesh, 2.5)
+    xb = wl.x.copy()
+    xb[3, 1] = 100.0                         # outside the walls
+    xt = torch.tensor(xb, device="cuda")
+    with pytest.raises(A.AicaError) as e:
+        A.aica_bin(d, xt)
+    assert e.value.code == A.AICA_E_UNLOCATED
+    xb[3, 1] = float("nan")
+    with pytest.raises(A.AicaError) as e:
+        A.aica_bin(d, torch.tensor(xb, device="cuda"))
+    assert e.value.code == A.AICA_E_UNLOCATED
+    x = torch.tensor(wl.x, device="cuda")
+    A.aica_bin(d, x)
+    other = x.clone()
+    with pytest.raises(A.AicaError) as e:
+        A.aica_forces(d, other, None, [1.0], [1.0], precision="fp64")
+    assert e.value.code == A.AICA_E_INVAL
+
+
+def test_deterministic_repeat(A):
+    import torch
+    wl = W.config1()
+    d, x, F1, uw1, n1 = run_gpu(A, wl, "fp32")
+    F2, uw2, n2 = A.aica_forces(d, x, None, wl.eps, wl.sigma, precision="fp32")
+    assert np.array_equal(F1, F2.double().cpu().numpy())
+    assert np.array_equal(uw1, uw2.cpu().numpy())
+
+
+def test_config2_walls_jittered(A, oracle):
+    wl = W.config2()
+    e64 = check_case(A, oracle, wl, "fp64", 1e-12, 1e-12)
+    e32 = check_case(A, oracle, wl, "fp32", 1e-5, 1e-6)
+    _note(f"config2 e_F fp64={e64:.3e} fp32={e32:.3e}")
+
+
+def test_config4_full_size_sampled_rows(A, oracle):
+    """219,488-molecule binary mixture at full size: the FP32 and FP64 forces on 600 sampled
+    rows against the oracle (each row summed over all molecules), exact pair counts per row via
+    the total, and zero net force."""
+    wl = W.config4()
+    rows = np.random.default_rng(40).choice(wl.n, 600, replace=False)
+    Fr, Ur, Wr, cnt = oracle.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, rows)
+    rms = np.sqrt((Fr ** 2).sum(1).mean())
+    d = A.DIL(wl.mesh, wl.rcut)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        _, x, F, uw, npairs = run_gpu(A, wl, prec, dil=d)
+        err = np.sqrt(((F[rows] - Fr) ** 2).sum(1)).max() / rms
+        _note(f"config4 {prec} sampled e_F = {err:.3e}, npairs = {npairs}")
+        assert err < tol, err
+        assert abs(F.sum(0)).max() < (1e-9 if prec == "fp64" else 1e-2) * np.abs(F).sum(0).max()
