@@ -1,0 +1,212 @@
+"""Benchmark: Lennard-Jones pair interactions per second of the AICA hot path on one MI355X.
+
+One step = one pass of the whole per-step path over one batch of synthetic input:
+  aica_bin (locate, CSR occupancy, work list) + aica_forces + aica_forces_adjoint,
+in FP32 pair arithmetic (compensated FP32 force sums, FP64 energy and virial).
+The same step is also timed in FP64, and the forward alone in both precisions.
+
+Prints ONE JSON line (rank 0).  `value` = npairs * steps / (timed seconds) for the
+FP32 forward+adjoint step.  `roofline` is the dominant kernel's algorithmic
+FLOP rate (HIP events on the stream the kernel runs on) against the FP32 vector
+peak; `cpu_baseline` is the FP64 oracle timed on a bounded sample of rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LJ pair interactions/s (fwd, fwd+adjoint), FP32 vs FP64 GPU at stated error"
+FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic FLOPs (FMA = 2, reciprocal = 1): forward per pair inside the cut-off, per rejected
+# candidate (difference, squared distance, compare), adjoint per pair inside the cut-off
+FLOP_FWD_PAIR, FLOP_REJECT, FLOP_ADJ_PAIR = 31, 8, 60
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_cs_0702131_amd import workloads as W
+    if name == "channel":
+        return W.config5()
+    if name == "binary":
+        return W.config4()
+    if name == "random":
+        return W.config2()
+    if name == "fcc864":
+        return W.config1()
+    if name.startswith("channel@"):
+        return W.config5(scale=float(name.split("@")[1]))
+    raise SystemExit(f"unknown workload {name}")
+
+
+def timed_steps(A, d, x, sp, wl, G, precision, steps, warmup, adjoint=True):
+    import torch
+    st = torch.cuda.current_stream()
+    for _ in range(warmup):
+        A.aica_bin(d, x)
+        F, uw, npairs = A.aica_forces(d, x, sp, wl.eps, wl.sigma, precision=precision)
+        if adjoint:
+            A.aica_forces_adjoint(d, x, G, 0.1, sp, wl.eps, wl.sigma, precision=precision)
+    torch.cuda.synchronize()
+    for k in ("pair_fwd", "pair_adj", "bin", "finalize"):
+        d.profile_read(k, reset=True)
+    d.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        A.aica_bin(d, x)
+        F, uw, npairs = A.aica_forces(d, x, sp, wl.eps, wl.sigma, precision=precision)
+        if adjoint:
+            A.aica_forces_adjoint(d, x, G, 0.1, sp, wl.eps, wl.sigma, precision=precision)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    d.profile(False)
+    prof = {k: d.profile_read(k, reset=True) for k in ("pair_fwd", "pair_adj", "bin", "finalize")}
+    return t, prof, F, uw, int(npairs.item())
+
+
+def cpu_baseline(wl, seconds_target, F32, F64, rng_seed=7):
+    """Time the FP64 oracle on a bounded sample of rows (each row against every molecule and image),
+    extrapolate to all rows, and compare the GPU forces on the same rows."""
+    from oracle import oracle as O
+    O.lib()
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    rng = np.random.default_rng(rng_seed)
+    n = wl.n
+    # calibrate on a few rows, then size the sample for the time target
+    r0 = rng.choice(n, min(n, 4 * cores), replace=False)
+    t = time.perf_counter()
+    O.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, r0)
+    per_row = (time.perf_counter() - t) / len(r0)
+    nrows = int(min(n, max(len(r0), seconds_target / max(per_row, 1e-9))))
+    rows = rng.choice(n, nrows, replace=False)
+    t = time.perf_counter()
+    Fr, Ur, Wr, cnt = O.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, rows)
+    t = time.perf_counter() - t
+    t_full = t * n / nrows
+    rms = np.sqrt((Fr ** 2).sum(1).mean())
+    errs = {}
+    for name, F in (("fp32", F32), ("fp64", F64)):
+        if F is not None:
+            errs[name] = float(np.sqrt(((F[rows] - Fr) ** 2).sum(1)).max() / rms)
+    return {"seconds": t, "rows": nrows, "t_full": t_full, "cores": cores, "row_pairs": int(cnt.sum()),
+            "errors": errs}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="channel")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs (processor referral "
+                                   "and halo exchange) are not part of it", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_cs_0702131_amd as A
+    from paper_cs_0702131_amd import workloads as W
+
+    t0 = time.perf_counter()
+    wl = workload(args.workload)
+    log(f"workload {wl.name}: {wl.mesh.n_cells} cells, {wl.n} molecules ({time.perf_counter() - t0:.1f}s)")
+    t0 = time.perf_counter()
+    d = A.DIL(wl.mesh, wl.rcut)
+    info = d.info()
+    log(f"interaction lists: {info['n_dil']} cell pairs in {info['build_seconds']:.1f}s")
+
+    dev = torch.device("cuda:0")
+    x32 = torch.tensor(wl.x, dtype=torch.float32, device=dev)
+    x64 = torch.tensor(wl.x, dtype=torch.float64, device=dev)
+    sp = torch.tensor(wl.species, dtype=torch.int32, device=dev)
+    G = wl.extra.get("G")
+    if G is None:
+        G = W.qround(np.random.default_rng(9).standard_normal((wl.n, 3)))
+    G32 = torch.tensor(G, dtype=torch.float32, device=dev)
+    G64 = torch.tensor(G, dtype=torch.float64, device=dev)
+    A.aica_bin(d, x32)
+    info = d.info()
+    dil_cand, lane_pairs = d.work_stats()
+    log(f"groups {info['n_groups']} group pairs {info['n_group_pairs']} ({info['group_seconds']:.1f}s); "
+        f"DIL candidates {dil_cand}, lane pairs {lane_pairs}")
+
+    res = {}
+    t, prof, F32, uw32, npairs = timed_steps(A, d, x32, sp, wl, G32, "fp32", args.steps, args.warmup)
+    res["fp32_fwd_adj"] = (t, prof)
+    log(f"fp32 fwd+adj: {1e3 * t / args.steps:.3f} ms/step, npairs {npairs}")
+    t, prof, F32, uw32, _ = timed_steps(A, d, x32, sp, wl, G32, "fp32", args.steps, 1, adjoint=False)
+    res["fp32_fwd"] = (t, prof)
+    F32n = F32.double().cpu().numpy()
+    F64n = None
+    if not args.no_fp64:
+        t, prof, F64, uw64, npairs64 = timed_steps(A, d, x64, sp, wl, G64, "fp64", args.steps, args.warmup)
+        res["fp64_fwd_adj"] = (t, prof)
+        t, prof, F64, uw64, npairs64 = timed_steps(A, d, x64, sp, wl, G64, "fp64", args.steps, 1, adjoint=False)
+        res["fp64_fwd"] = (t, prof)
+        F64n = F64.cpu().numpy()
+        assert npairs64 == npairs, (npairs64, npairs)
+
+    K = args.steps
+    t_main, prof_main = res["fp32_fwd_adj"]
+    value = npairs * K / t_main
+    breakdown = {}
+    for key, (t, prof) in res.items():
+        breakdown[key] = {"ms_per_step": 1e3 * t / K, "pairs_per_s": npairs * K / t,
+                          **{f"{k}_ms": v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}}
+    # dominant kernel of the FP32 step and its algorithmic FLOP rate
+    fwd_ms = prof_main["pair_fwd"][0] / prof_main["pair_fwd"][1]
+    adj_ms = prof_main["pair_adj"][0] / prof_main["pair_adj"][1]
+    rejected = dil_cand - npairs
+    if adj_ms >= fwd_ms:
+        kname, kms, flops = "pair_adj", adj_ms, FLOP_ADJ_PAIR * npairs + FLOP_REJECT * rejected
+    else:
+        kname, kms, flops = "pair_fwd", fwd_ms, FLOP_FWD_PAIR * npairs + FLOP_REJECT * rejected
+    achieved = flops / (kms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None, "kernel": kname,
+                "kernel_ms": kms, "algorithmic_flop": flops}
+
+    cpu = None
+    errors = {"npairs": npairs}
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(wl, args.cpu_seconds, F32n, F64n)
+        cpu = {"value": npairs / cb["t_full"], "unit": "pair interactions/s", "cores": cb["cores"],
+               "kind": "oracle",
+               "sample": f"{cb['rows']} random rows of {wl.n} (each against all molecules and images, "
+                         f"{cb['seconds']:.1f}s), extrapolated linearly to all rows"}
+        errors.update({f"e_F_{k}": v for k, v in cb["errors"].items()})
+        errors["e_F_rows"] = cb["rows"]
+    if F64n is not None:
+        errors["e_F_fp32_vs_fp64_gpu"] = float(np.sqrt(((F32n - F64n) ** 2).sum(1)).max()
+                                               / np.sqrt((F64n ** 2).sum(1).mean()))
+        errors["dU_fp32_vs_fp64"] = float(abs(uw32[0].item() - uw64[0].item()) / abs(uw64[0].item()))
+        errors["dW_fp32_vs_fp64"] = float(abs(uw32[1].item() - uw64[1].item()) / abs(uw64[1].item()))
+
+    out = {"metric": METRIC, "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t_main / K, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": wl.name, "cells": wl.mesh.n_cells, "molecules": wl.n, "npairs": npairs,
+                      "step": "aica_bin + aica_forces + aica_forces_adjoint", "parallelism": "single GPU",
+                      "dil_cell_pairs": info["n_dil"], "dil_candidates": dil_cand, "lane_pairs": lane_pairs},
+           "breakdown": breakdown, "errors": errors, "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

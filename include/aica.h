@@ -153,6 +153,13 @@ typedef struct aica_info {
 } aica_info;
 int aica_dil_info(const aica_dil *dil, aica_info *info);
 
+/* Work of the last aica_bin's occupancy, counted on the host:
+ *   dil_candidates: molecule pairs the interaction lists make candidates (the method's own
+ *                   candidate set: sum over listed cell pairs of n_c n_d, plus n_c (n_c - 1) / 2 per cell);
+ *   lane_pairs:     pair evaluations the GPU tile schedule executes (16 x 16 per tile, 16 x 8 per
+ *                   half tile), padding included. */
+int aica_work_stats(const aica_dil *dil, int64_t *dil_candidates, int64_t *lane_pairs);
+
 /* Kernel timing with HIP events on the caller's stream: enable, then read the
  * accumulated milliseconds and launch count of a named kernel
  * ("pair_fwd", "pair_adj", "bin", "finalize"), and reset. */

@@ -66,6 +66,12 @@ class DIL:
         check(lib().aica_dil_info(self.h, C.byref(inf)))
         return {k: getattr(inf, k) for k, _ in aica_info._fields_}
 
+    def work_stats(self):
+        """(DIL candidate pairs, executed lane-pair evaluations) of the last binning."""
+        a, b = C.c_int64(), C.c_int64()
+        check(lib().aica_work_stats(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def profile(self, enable=True):
         check(lib().aica_profile(self.h, 1 if enable else 0))
 

@@ -23,7 +23,7 @@ ERROR_NAMES = {AICA_E_INVAL: "AICA_E_INVAL", AICA_E_MESH: "AICA_E_MESH", AICA_E_
                AICA_E_UNLOCATED: "AICA_E_UNLOCATED", AICA_E_NOMEM: "AICA_E_NOMEM", AICA_E_HIP: "AICA_E_HIP"}
 
 EXPORTED = ["aica_build_dil", "aica_bin", "aica_forces", "aica_forces_adjoint", "aica_dil_export",
-            "aica_pairs_export", "aica_bin_export", "aica_dil_info", "aica_profile", "aica_profile_read",
+            "aica_pairs_export", "aica_bin_export", "aica_dil_info", "aica_work_stats", "aica_profile", "aica_profile_read",
             "aica_last_error", "aica_dil_free"]
 
 
@@ -72,6 +72,7 @@ def lib():
         L.aica_pairs_export.argtypes = [p, p, C.POINTER(aica_params), i64, p, p, p, p, p]
         L.aica_bin_export.argtypes = [p, p, p, p]
         L.aica_dil_info.argtypes = [p, C.POINTER(aica_info)]
+        L.aica_work_stats.argtypes = [p, p, p]
         L.aica_profile.argtypes = [p, i32]
         L.aica_profile_read.argtypes = [p, C.c_char_p, p, p, i32]
         L.aica_last_error.restype = C.c_char_p

@@ -859,8 +859,15 @@ int aica_build_dil(const aica_mesh *mesh, double rcut, double guard, aica_dil **
   }
   h->rcut = rcut;
   h->guard = guard;
+  const bool verbose = getenv("AICA_VERBOSE") != nullptr;
+  auto t1 = std::chrono::steady_clock::now();
   spatial_order(h->geo, h->order, h->rank);
+  auto t2 = std::chrono::steady_clock::now();
   rc = build_cell_pairs(h->geo, h->order, h->rank, rcut + guard, h->pairs);
+  if (verbose)
+    fprintf(stderr, "aica_build_dil: geometry %.2fs order %.2fs pairs %.2fs (%zu)\n",
+            std::chrono::duration<double>(t1 - t0).count(), std::chrono::duration<double>(t2 - t1).count(),
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t2).count(), h->pairs.size());
   if (rc) {
     delete h;
     return rc;
@@ -1202,6 +1209,40 @@ int aica_dil_info(const aica_dil *h, aica_info *info) {
   info->build_seconds = h->build_seconds;
   info->group_seconds = h->group_seconds;
   info->lane_steps = -1;
+  return AICA_OK;
+}
+
+int aica_work_stats(const aica_dil *h, int64_t *dil_candidates, int64_t *lane_pairs) {
+  if (!h) return fail(AICA_E_INVAL, "handle is NULL");
+  if (!h->bin_valid) return fail(AICA_E_INVAL, "aica_bin must succeed first");
+  const int64_t nc = h->geo.nc, ng = h->grp.ng;
+  std::vector<int32_t> cs(nc + 1), gs(ng + 1);
+  HIPCHK(hipMemcpy(cs.data(), h->d_cell_start.p, 4 * (nc + 1), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(gs.data(), h->d_g_start.p, 4 * (ng + 1), hipMemcpyDeviceToHost));
+  if (dil_candidates) {
+    int64_t cand = 0;
+    for (int64_t s = 0; s < nc; ++s) {
+      const int64_t n = cs[s + 1] - cs[s];
+      cand += n * (n - 1) / 2;
+    }
+    for (const CellPair &p : h->pairs) cand += (int64_t)(cs[p.sc + 1] - cs[p.sc]) * (cs[p.sd + 1] - cs[p.sd]);
+    *dil_candidates = cand;
+  }
+  if (lane_pairs) {
+    int64_t lp = 0;
+    for (int64_t a = 0; a < ng; ++a) {
+      const int64_t ca = (gs[a + 1] - gs[a] + kRow - 1) / kRow;
+      for (int64_t e = h->grp.e_off[a]; e < h->grp.e_off[a + 1]; ++e) {
+        const int64_t B = h->grp.e_B[e];
+        const int64_t cb = (gs[B + 1] - gs[B] + kRow - 1) / kRow;
+        if (e == h->grp.e_off[a])
+          lp += ca * kRow * 8 + (ca * (ca - 1) / 2) * kRow * kRow;  // half tiles + upper chunk pairs
+        else
+          lp += ca * cb * kRow * kRow;
+      }
+    }
+    *lane_pairs = lp;
+  }
   return AICA_OK;
 }
 

@@ -33,6 +33,8 @@ struct Geometry {
   std::vector<double> ccen;      // [nc][3] vertex mean of the cell's distinct vertices
   std::vector<double> lo, hi;    // [nc][3] bounding boxes
   std::vector<double> vol;       // [nc] cell volumes (sum of tetrahedra)
+  std::vector<double> r_in;      // [nc] radius of a ball about the centroid inside the cell
+  std::vector<double> r_out;     // [nc] largest centroid-to-vertex distance
   std::vector<int64_t> cv_off;   // [nc+1] distinct vertices of each cell
   std::vector<int32_t> cv;
   double dom_lo[3], dom_hi[3];   // mesh bounding box

@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -160,6 +161,8 @@ int build_geometry(const aica_mesh *m, Geometry &g) {
   g.lo.assign(3 * g.nc, 0.0);
   g.hi.assign(3 * g.nc, 0.0);
   g.vol.assign(g.nc, 0.0);
+  g.r_in.assign(g.nc, 0.0);
+  g.r_out.assign(g.nc, 0.0);
   std::vector<int64_t> bad(host_threads() + 1, -1);
   std::atomic<int64_t> first_bad(-1);
   parallel_for(g.nc, [&](int64_t b, int64_t e, int) {
@@ -189,8 +192,12 @@ int build_geometry(const aica_mesh *m, Geometry &g) {
       }
       // tetrahedra (cell centroid, face centroid, edge) must all have positive volume
       V3 cc = mk(&g.ccen[3 * c]);
-      double vol = 0;
+      double vol = 0, rin = 1e300, rout = 0;
       bool ok = true;
+      for (size_t j = 0; j < ids.size(); ++j) {
+        V3 v = mk(&g.pts[3 * (int64_t)ids[j]]) - cc;
+        rout = std::max(rout, std::sqrt(dot(v, v)));
+      }
       for (int64_t k = g.cf_off[c]; k < g.cf_off[c + 1]; ++k) {
         int32_t f = g.cf[k];
         V3 fc = mk(&g.fcen[3 * (int64_t)f]);
@@ -202,9 +209,17 @@ int build_geometry(const aica_mesh *m, Geometry &g) {
           double v = dot(fc - cc, cross(a - cc, bb - cc)) / 6.0;
           if (!(v > 0)) ok = false;
           vol += v;
+          // distance from the centroid to the plane of the face triangle = 3 V / area
+          V3 n = cross(a - fc, bb - fc);
+          double area = 0.5 * std::sqrt(dot(n, n));
+          if (area > 0) rin = std::min(rin, 3.0 * v / area);
         }
       }
       g.vol[c] = vol;
+      // every point within rin of the centroid lies in the cone of some face triangle and on the inner
+      // side of that triangle's plane, hence inside the cell
+      g.r_in[c] = std::max(0.0, rin) * (1.0 - 1e-12);
+      g.r_out[c] = rout * (1.0 + 1e-12);
       if (!ok) {
         int64_t exp = -1;
         first_bad.compare_exchange_strong(exp, c);
@@ -384,15 +399,53 @@ static inline double box_gap2(const double *alo, const double *ahi, const double
 }
 
 // Is the closest distance between cell c and cell d translated by T below R?
+// Compact per-cell bounds in sorted order for the candidate scan.
+struct CellBox {
+  double lo[3], hi[3], cen[3], rin, rout;
+};
+
+// Cheap classification: 1 = in range, 0 = not, -1 = undecided (needs the exact test).
+static inline int quick_range(const CellBox &C, const CellBox &D, const V3 &T, double R) {
+  const double R2 = R * R;
+  double g2 = 0;
+  const double Tq[3] = {T.x, T.y, T.z};
+  for (int q = 0; q < 3; ++q) {
+    const double lo = D.lo[q] + Tq[q], hi = D.hi[q] + Tq[q];
+    double gap = 0;
+    if (lo > C.hi[q]) gap = lo - C.hi[q];
+    if (C.lo[q] > hi) gap = C.lo[q] - hi;
+    g2 += gap * gap;
+  }
+  if (g2 >= R2) return 0;
+  // balls of radius r_in about the centroids lie inside the cells (upper bound on the distance);
+  // balls of radius r_out contain them (lower bound)
+  const double d0 = C.cen[0] - D.cen[0] - Tq[0], d1 = C.cen[1] - D.cen[1] - Tq[1], d2 = C.cen[2] - D.cen[2] - Tq[2];
+  const double cd = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  if (cd - C.rin - D.rin < R) return 1;
+  if (cd - C.rout - D.rout >= R) return 0;
+  return -1;
+}
+
+// Exact test (after quick_range returned -1): vertex pairs, then boundary triangle pairs.
 static bool cells_in_range(const Geometry &g, int32_t c, int32_t d, const V3 &T, double R, CellTris &tc,
                            CellTris &td) {
   const double R2 = R * R;
   double dlo[3] = {g.lo[3 * (int64_t)d] + T.x, g.lo[3 * (int64_t)d + 1] + T.y, g.lo[3 * (int64_t)d + 2] + T.z};
   double dhi[3] = {g.hi[3 * (int64_t)d] + T.x, g.hi[3 * (int64_t)d + 1] + T.y, g.hi[3 * (int64_t)d + 2] + T.z};
-  if (box_gap2(&g.lo[3 * (int64_t)c], &g.hi[3 * (int64_t)c], dlo, dhi) >= R2) return false;
-  // the cell centroid is inside its (star-shaped) cell, so it bounds the distance from above
-  V3 dc = mk(&g.ccen[3 * (int64_t)c]) - (mk(&g.ccen[3 * (int64_t)d]) + T);
-  if (dot(dc, dc) < R2) return true;
+  // separating axis along the centroid direction: every cell lies in the convex hull of its vertices,
+  // so a projection gap of at least R proves the cells are out of range
+  {
+    V3 u = (mk(&g.ccen[3 * (int64_t)d]) + T) - mk(&g.ccen[3 * (int64_t)c]);
+    const double uu = std::sqrt(dot(u, u));
+    if (uu > 0) {
+      u = u * (1.0 / uu);
+      double cmax = -1e300, dmin = 1e300;
+      for (int64_t i = g.cv_off[c]; i < g.cv_off[c + 1]; ++i) cmax = std::max(cmax, dot(mk(&g.pts[3 * (int64_t)g.cv[i]]), u));
+      for (int64_t j = g.cv_off[d]; j < g.cv_off[d + 1]; ++j)
+        dmin = std::min(dmin, dot(mk(&g.pts[3 * (int64_t)g.cv[j]]) + T, u));
+      if (dmin - cmax >= R * (1.0 + 1e-12)) return false;
+    }
+  }
   for (int64_t i = g.cv_off[c]; i < g.cv_off[c + 1]; ++i) {
     V3 a = mk(&g.pts[3 * (int64_t)g.cv[i]]);
     for (int64_t j = g.cv_off[d]; j < g.cv_off[d + 1]; ++j) {
@@ -426,20 +479,35 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
                                    " vs " + std::to_string(L) + ")");
   }
   // uniform grid of cell centroids over the mesh bounding box
-  double bin = 0;
-  for (int q = 0; q < 3; ++q) bin = std::max(bin, 2.0 * g.max_half_ext[q]);
-  bin = std::max(bin, 1e-9);
+  // centroid bins about one mean cell size per axis
+  double binq[3];
+  const double hmean = std::cbrt(g.total_volume / (double)g.nc);
+  for (int q = 0; q < 3; ++q) binq[q] = std::max(hmean, 1e-9);
   int64_t nb[3];
-  for (int q = 0; q < 3; ++q) nb[q] = std::max<int64_t>(1, (int64_t)std::ceil((g.dom_hi[q] - g.dom_lo[q]) / bin));
+  for (int q = 0; q < 3; ++q) nb[q] = std::max<int64_t>(1, (int64_t)std::ceil((g.dom_hi[q] - g.dom_lo[q]) / binq[q]));
   while (nb[0] * nb[1] * nb[2] > 4 * g.nc + 64) {
-    bin *= 1.25;
-    for (int q = 0; q < 3; ++q) nb[q] = std::max<int64_t>(1, (int64_t)std::ceil((g.dom_hi[q] - g.dom_lo[q]) / bin));
+    for (int q = 0; q < 3; ++q) {
+      binq[q] *= 1.25;
+      nb[q] = std::max<int64_t>(1, (int64_t)std::ceil((g.dom_hi[q] - g.dom_lo[q]) / binq[q]));
+    }
   }
   const int64_t nbins = nb[0] * nb[1] * nb[2];
+  const double bin = std::max({binq[0], binq[1], binq[2]});
   auto bin_of = [&](double v, int q) {
-    int64_t b = (int64_t)std::floor((v - g.dom_lo[q]) / bin);
+    int64_t b = (int64_t)std::floor((v - g.dom_lo[q]) / binq[q]);
     return std::min<int64_t>(std::max<int64_t>(b, 0), nb[q] - 1);
   };
+  std::vector<CellBox> box(g.nc);
+  for (int64_t s = 0; s < g.nc; ++s) {
+    const int64_t c = order[s];
+    for (int q = 0; q < 3; ++q) {
+      box[s].lo[q] = g.lo[3 * c + q];
+      box[s].hi[q] = g.hi[3 * c + q];
+      box[s].cen[q] = g.ccen[3 * c + q];
+    }
+    box[s].rin = g.r_in[c];
+    box[s].rout = g.r_out[c];
+  }
   std::vector<int64_t> boff(nbins + 1, 0);
   std::vector<int32_t> bcell(g.nc);
   for (int64_t c = 0; c < g.nc; ++c) {
@@ -452,7 +520,7 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
     for (int64_t s = 0; s < g.nc; ++s) {  // in sorted order so bins list ascending sorted ids
       int64_t c = order[s];
       int64_t b = bin_of(g.ccen[3 * c], 0) + nb[0] * (bin_of(g.ccen[3 * c + 1], 1) + nb[1] * bin_of(g.ccen[3 * c + 2], 2));
-      bcell[fill[b]++] = (int32_t)c;
+      bcell[fill[b]++] = (int32_t)s;  // sorted id
     }
   }
   int nimg = 1;
@@ -465,12 +533,13 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
   const int64_t chunk = 2048;
   const int64_t nchunks = (g.nc + chunk - 1) / chunk;
   per_chunk.resize(nchunks);
-  std::atomic<int64_t> next(0);
+  std::atomic<int64_t> next(0), n_cand(0), n_exact(0);
   std::vector<std::thread> th;
   for (int t = 0; t < nt; ++t)
     th.emplace_back([&]() {
       CellTris tc, td;
       std::vector<CellPair> local;
+      int64_t stat_cand = 0, stat_exact = 0;
       for (;;) {
         int64_t ch = next.fetch_add(1);
         if (ch >= nchunks) break;
@@ -503,10 +572,15 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
                 for (int64_t x = b0[0]; x <= b1[0]; ++x) {
                   int64_t b = x + nb[0] * (y + nb[1] * z);
                   for (int64_t k = boff[b]; k < boff[b + 1]; ++k) {
-                    int32_t d = bcell[k];
-                    int32_t sd = rank[d];
+                    const int32_t sd = bcell[k];
                     if (sd < sc || (sd == sc && code <= 13)) continue;  // canonical half
-                    if (cells_in_range(g, c, d, T, R, tc, td)) {
+                    int q = quick_range(box[sc], box[sd], T, R);
+                    ++stat_cand;
+                    if (q < 0) {
+                      ++stat_exact;
+                      q = cells_in_range(g, c, order[sd], T, R, tc, td) ? 1 : 0;
+                    }
+                    if (q) {
                       CellPair p;
                       p.sc = (int32_t)sc;
                       p.sd = sd;
@@ -526,8 +600,13 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
         });
         per_chunk[ch] = local;
       }
+      n_cand += stat_cand;
+      n_exact += stat_exact;
     });
   for (auto &x : th) x.join();
+  if (getenv("AICA_VERBOSE"))
+    fprintf(stderr, "cell pairs: %lld candidates, %lld exact tests, %lld bins\n", (long long)n_cand.load(),
+            (long long)n_exact.load(), (long long)nbins);
   size_t total = 0;
   for (auto &v : per_chunk) total += v.size();
   out.clear();
