@@ -95,19 +95,22 @@ struct aica_dil {
   bool groups_ready = false;
   int64_t groups_for_n = -1;
   Groups grp;
-  DBuf d_orig, d_g_cell0, d_e_off, d_e_B, d_e_vec32, d_e_vec64, d_r_off, d_r_e;
+  DBuf d_orig, d_g_cell0, d_e_off, d_e_B, d_e_vec32, d_e_vec64, d_nl_off, d_nl_e, d_nl_d, d_nl_r, d_rcnt;
   // per step
   bool bin_valid = false;
   int64_t n = 0;
   const void *bin_pos = nullptr;
   int32_t bin_dtype = 0;
   int64_t jtotal = 0;
-  DBuf d_cell_of, d_count, d_cell_start, d_fill, d_perm, d_g_start, d_mol_group, d_jcnt, d_jb_off;
-  DBuf d_scan_tmp, d_status;
+  DBuf d_cell_of, d_count, d_cell_start, d_fill, d_perm, d_g_start, d_mol_group, d_jcnt, d_slot_base, d_cell_sorted;
+  DBuf d_scan_tmp, d_status, d_hint;
+  int64_t hint_n = -1;  // molecule count the hints belong to (-1: none)
   // force / adjoint workspace
   DBuf d_pos, d_own, d_jpart, d_gpart, d_gnp, d_gG, d_gpar;
   DBuf d_pairs, d_pcount;
   bool profiling = false;
+  uint32_t epoch = 0;          // tag of the reaction records written by the current call
+  size_t jpart_tagged = 0;     // bytes of d_jpart known to hold no valid tag
   std::map<std::string, Timer> timers;
 };
 
@@ -123,29 +126,37 @@ __device__ __forceinline__ double orient3(const double *a, const double *b, cons
   return u0 * (v1 * w2 - v2 * w1) + u1 * (v2 * w0 - v0 * w2) + u2 * (v0 * w1 - v1 * w0);
 }
 
-// Is p inside cell c: some tetrahedron (cell centroid, face centroid, edge) contains p, with a
-// relative tolerance of 1e-12 of that tetrahedron's volume.
+// Is p inside cell c: some tetrahedron (cell centroid cc, face centroid fc, edge v_k v_k+1) contains p,
+// with a relative tolerance tau of that tetrahedron's volume (tau = 1e-12 for membership; the
+// previous-cell fast path asks for tau = -1e-9, i.e. strictly inside).  The four barycentric tests of
+// tetrahedron k are: the outer face, orient(p, fc, v_k, v_k+1) >= -tol; the edge plane through cc,
+// orient(cc, p, v_k, v_k+1) >= -tol; and the two spoke planes (cc, fc, v_k), (cc, fc, v_k+1), whose
+// orientations s_k = orient(cc, fc, v_k, p) are shared by neighbouring tetrahedra of the fan.
 __device__ bool point_in_cell(const double *p, int32_t c, const double *pts, const int64_t *foff,
                               const int32_t *fpts, const double *fcen, const int64_t *cf_off, const int32_t *cf,
-                              const int8_t *cf_sgn, const double *ccen) {
+                              const int8_t *cf_sgn, const double *ccen, double tau) {
   const double cc[3] = {ccen[3 * (int64_t)c], ccen[3 * (int64_t)c + 1], ccen[3 * (int64_t)c + 2]};
   for (int64_t k = cf_off[c]; k < cf_off[c + 1]; ++k) {
     const int32_t f = cf[k];
     const double fc[3] = {fcen[3 * (int64_t)f], fcen[3 * (int64_t)f + 1], fcen[3 * (int64_t)f + 2]};
     const int64_t b0 = foff[f], len = foff[f + 1] - b0;
+    const bool rev = cf_sgn[k] < 0;
+    auto vtx = [&](int64_t j) -> const double * {
+      const int64_t jj = rev ? (len - j) % len : j;  // reversed loop for the neighbour side
+      return pts + 3 * (int64_t)fpts[b0 + jj];
+    };
+    const double *v0 = vtx(0);
+    double s_first = orient3(cc, fc, v0, p), s_prev = s_first;
+    const double *vp = v0;
     for (int64_t j = 0; j < len; ++j) {
-      int64_t ia = fpts[b0 + j], ib = fpts[b0 + (j + 1 == len ? 0 : j + 1)];
-      if (cf_sgn[k] < 0) {
-        int64_t t = ia;
-        ia = ib;
-        ib = t;
-      }
-      const double *a = pts + 3 * ia, *b = pts + 3 * ib;
-      const double v = orient3(cc, fc, a, b);
-      const double tol = -1e-12 * fabs(v);
-      if (orient3(p, fc, a, b) >= tol && orient3(cc, p, a, b) >= tol && orient3(cc, fc, p, b) >= tol &&
-          orient3(cc, fc, a, p) >= tol)
+      const double *vn = vtx(j + 1 == len ? 0 : j + 1);
+      const double s_next = (j + 1 == len) ? s_first : orient3(cc, fc, vn, p);
+      const double v = orient3(cc, fc, vp, vn);
+      const double tol = -tau * fabs(v);
+      if (s_prev >= tol && -s_next >= tol && orient3(p, fc, vp, vn) >= tol && orient3(cc, p, vp, vn) >= tol)
         return true;
+      s_prev = s_next;
+      vp = vn;
     }
   }
   return false;
@@ -157,12 +168,17 @@ __global__ void k_locate(const PT *__restrict__ pos, int64_t n, const double *pt
                          const int8_t *cf_sgn, const double *ccen, const double *bb, const int32_t *rank,
                          const int64_t *gb_off, const int32_t *gb_cell, double glo0, double glo1, double glo2,
                          double gh, int64_t nb0, int64_t nb1, int64_t nb2, int32_t *cell_sorted,
-                         int32_t *count, unsigned long long *status) {
+                         int32_t *count, unsigned long long *status, int32_t *hint) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
   int32_t found = -1;
-  if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
+  // tracking fast path: a molecule strictly inside its previous cell is in no other cell
+  const int32_t h0 = hint ? hint[i] : -1;
+  if (h0 >= 0 && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) &&
+      point_in_cell(p, h0, pts, foff, fpts, fcen, cf_off, cf, cf_sgn, ccen, -1e-9))
+    found = h0;
+  if (found < 0 && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
     const double f0 = floor((p[0] - glo0) / gh), f1 = floor((p[1] - glo1) / gh), f2 = floor((p[2] - glo2) / gh);
     if (f0 >= 0 && f1 >= 0 && f2 >= 0 && f0 < (double)nb0 && f1 < (double)nb1 && f2 < (double)nb2) {
       const int64_t b = (int64_t)f0 + nb0 * ((int64_t)f1 + nb1 * (int64_t)f2);
@@ -170,7 +186,7 @@ __global__ void k_locate(const PT *__restrict__ pos, int64_t n, const double *pt
         const int32_t c = gb_cell[k];
         const double *B = bb + 6 * (int64_t)c;
         if (p[0] < B[0] || p[1] < B[1] || p[2] < B[2] || p[0] > B[3] || p[1] > B[4] || p[2] > B[5]) continue;
-        if (point_in_cell(p, c, pts, foff, fpts, fcen, cf_off, cf, cf_sgn, ccen)) {
+        if (point_in_cell(p, c, pts, foff, fpts, fcen, cf_off, cf, cf_sgn, ccen, 1e-12)) {
           found = c;
           break;
         }
@@ -185,6 +201,7 @@ __global__ void k_locate(const PT *__restrict__ pos, int64_t n, const double *pt
     cell_sorted[i] = s;
     atomicAdd(&count[s], 1);
   }
+  if (hint) hint[i] = found;
 }
 
 // ---- exclusive scan of int32 counts into OutT offsets (out[n] = total)
@@ -414,256 +431,16 @@ struct LaneLJ {
 __device__ __forceinline__ float fast_rcp(float s) { return __builtin_amdgcn_rcpf(s); }
 __device__ __forceinline__ double fast_rcp(double s) { return 1.0 / s; }
 
-// One pair: d = x_i - x_j (image already applied), returns g (force factor), u and whether the pair
-// is inside the cut-off.  The FP32 decision is made exact near r_cut: when |s - rc^2| is within the
-// FP32 rounding band, s is recomputed in FP64 from the exact FP32 differences.
-template <typename T>
-__device__ __forceinline__ void lj_pair(T dx, T dy, T dz, T sig2, T e24, T e4, const LJTab &tab, bool extra, T &g,
-                                        T &u, T &s_out, bool &in) {
-  T s;
-  if constexpr (sizeof(T) == 4) {
-    s = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    bool inn = s < tab.rc2;
-    if (fabsf(s - tab.rc2) <= tab.band) {
-      const double sd = (double)dx * (double)dx + (double)dy * (double)dy + (double)dz * (double)dz;
-      inn = sd < tab.rc2d;
-    }
-    in = inn && extra;
-  } else {
-    s = fma(dx, dx, fma(dy, dy, dz * dz));
-    in = (s < tab.rc2d) && extra;
-  }
-  const T inv = fast_rcp(s);
-  const T sr2 = sig2 * inv;
-  const T sr6 = sr2 * sr2 * sr2;
-  const T gg = e24 * inv * sr6 * (sr6 + sr6 - (T)1);
-  const T uu = e4 * sr6 * (sr6 - (T)1);
-  g = in ? gg : (T)0;
-  u = in ? uu : (T)0;
-  s_out = s;
-}
-
 template <typename T>
 __device__ __forceinline__ T far_i() { return (T)1e15; }
 template <typename T>
 __device__ __forceinline__ T far_j() { return (T)-1e15; }
 
-// MODE 0: forces, energy, virial.  MODE 1: export the pair list.
-//
-// One wave per interaction group A.  The wave's four 16-lane rows hold the same i-chunk (16
-// molecules of A, one per lane) and work through A's group-pair entries round-robin; for each
-// entry (B, image) the row stages 16 j-molecules of B in LDS and runs a 16-step rotation: at step s
-// lane c pairs i_c with j_{(c+s) mod 16}.  F_i stays in the lane; the reaction -F goes into a
-// per-row accumulator that rotates one lane per step (DPP row_ror) so that after the tile lane c
-// holds the total reaction on j_c, which is stored (no atomics) into the entry's j-slot buffer.
-// The self entry (A, A, 0) uses half tiles so each unordered pair inside A is evaluated once.
-template <typename T, int MIX, int MODE, bool COMP>
-__global__ __launch_bounds__(kBlock) void k_pair_fwd(
-    const typename Vec4<T>::type *__restrict__ pos, const int32_t *__restrict__ g_start,
-    const int64_t *__restrict__ e_off, const int32_t *__restrict__ e_B, const typename Vec4<T>::type *__restrict__ e_vec,
-    const int64_t *__restrict__ jb_off, T *__restrict__ jpart, int64_t J, T *__restrict__ own, int64_t N,
-    double *__restrict__ gpart, unsigned long long *__restrict__ gnp, int64_t ng, int64_t nblocks_padded, LJTab tab,
-    const int32_t *__restrict__ perm, int64_t cap, int32_t *__restrict__ pairs_out,
-    unsigned long long *__restrict__ pair_count) {
-  using V4 = typename Vec4<T>::type;
-  __shared__ V4 lds[kWavesPerBlock][64];
-  const int lane = threadIdx.x & 63, row = lane >> 4, c = lane & 15, w = threadIdx.x >> 6;
-  const int64_t a = xcd_block(blockIdx.x, nblocks_padded) * kWavesPerBlock + w;
-  if (a >= ng) return;
-  V4 *my = &lds[w][row * kRow];
-  const int32_t m0 = g_start[a], nA = g_start[a + 1] - m0;
-  const int64_t e0 = e_off[a], e1 = e_off[a + 1];
-  double Ul = 0, Wl = 0;
-  unsigned npl = 0;
-  for (int ib = 0; ib < nA; ib += kRow) {
-    const int ni = min(kRow, nA - ib);
-    V4 pi;
-    if (c < ni) {
-      pi = pos[m0 + ib + c];
-    } else {
-      pi.x = pi.y = pi.z = far_i<T>();
-      pi.w = (T)0;
-    }
-    LaneLJ<T, MIX> lp;
-    lp.init(tab, c < ni ? type_of<T>(pi.w) : 0);
-    T fx = 0, fy = 0, fz = 0, cx = 0, cy = 0, cz = 0;
-    for (int64_t e = e0 + row; e < e1; e += 4) {
-      const int32_t B = e_B[e];
-      const V4 ov = e_vec[e];
-      const int32_t mb0 = g_start[B], nB = g_start[B + 1] - mb0;
-      const bool self = (e == e0);
-      const T xi = pi.x - ov.x, yi = pi.y - ov.y, zi = pi.z - ov.z;
-      const int64_t jo = jb_off[e];
-      for (int jb = self ? ib : 0; jb < nB; jb += kRow) {
-        const int nj = min(kRow, nB - jb);
-        V4 pj;
-        if (c < nj) {
-          pj = pos[mb0 + jb + c];
-        } else {
-          pj.x = pj.y = pj.z = far_j<T>();
-          pj.w = (T)0;
-        }
-        my[c] = pj;
-        wave_lds_sync();
-        T tfx = 0, tfy = 0, tfz = 0, ax = 0, ay = 0, az = 0, tu = 0, tw = 0;
-        const bool half = self && (jb == ib);
-        auto step = [&](int s, bool extra) {
-          const int slot = (c + s) & 15;
-          const V4 q = my[slot];
-          const T dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-          T sig2, e24, e4;
-          lp.get(tab, type_of<T>(q.w), sig2, e24, e4);
-          T g, u, s2;
-          bool in;
-          lj_pair<T>(dx, dy, dz, sig2, e24, e4, tab, extra, g, u, s2, in);
-          if (MODE == 0) {
-            const T gx = g * dx, gy = g * dy, gz = g * dz;
-            tfx += gx;
-            tfy += gy;
-            tfz += gz;
-            ax = ror15(ax) - gx;
-            ay = ror15(ay) - gy;
-            az = ror15(az) - gz;
-            tu += u;
-            tw += g * s2;
-            npl += in ? 1u : 0u;
-          } else {
-            if (in) {
-              const unsigned long long k = atomicAdd(pair_count, 1ull);
-              if ((int64_t)k < cap) {
-                pairs_out[3 * k] = perm[m0 + ib + c];
-                pairs_out[3 * k + 1] = perm[mb0 + jb + slot];
-                pairs_out[3 * k + 2] = type_of<T>(ov.w);
-              }
-            }
-          }
-        };
-        if (half) {
-#pragma unroll
-          for (int s = 1; s < 8; ++s) step(s, true);
-          step(8, c < 8);
-        } else {
-#pragma unroll
-          for (int s = 0; s < 16; ++s) step(s, true);
-        }
-        if (MODE == 0) {
-          // after the last step s_last lane c holds the reaction on slot (c + s_last) mod 16
-          const int ws = (c + (half ? 8 : 15)) & 15;
-          if (ws < nj) {
-            const int64_t k = jo + jb + ws;
-            if (ib == 0) {
-              jpart[k] = ax;
-              jpart[J + k] = ay;
-              jpart[2 * J + k] = az;
-            } else {
-              jpart[k] += ax;
-              jpart[J + k] += ay;
-              jpart[2 * J + k] += az;
-            }
-          }
-          if (COMP) {
-            T s, err;
-            two_sum(fx, tfx, s, err);
-            fx = s;
-            cx += err;
-            two_sum(fy, tfy, s, err);
-            fy = s;
-            cy += err;
-            two_sum(fz, tfz, s, err);
-            fz = s;
-            cz += err;
-          } else {
-            fx += tfx;
-            fy += tfy;
-            fz += tfz;
-          }
-          Ul += (double)tu;
-          Wl += (double)tw;
-        }
-        wave_lds_sync();
-      }
-    }
-    if (MODE == 0) {
-      // combine the four rows' partial F_i (lanes c, c+16, c+32, c+48)
-#pragma unroll
-      for (int o = 16; o <= 32; o <<= 1) {
-        const T ox = __shfl_xor(fx, o, 64), oy = __shfl_xor(fy, o, 64), oz = __shfl_xor(fz, o, 64);
-        const T pcx = __shfl_xor(cx, o, 64), pcy = __shfl_xor(cy, o, 64), pcz = __shfl_xor(cz, o, 64);
-        if (COMP) {
-          T s, err;
-          two_sum(fx, ox, s, err);
-          fx = s;
-          cx += pcx + err;
-          two_sum(fy, oy, s, err);
-          fy = s;
-          cy += pcy + err;
-          two_sum(fz, oz, s, err);
-          fz = s;
-          cz += pcz + err;
-        } else {
-          fx += ox;
-          fy += oy;
-          fz += oz;
-        }
-      }
-      if (row == 0 && c < ni) {
-        const int64_t m = m0 + ib + c;
-        own[m] = fx;
-        own[N + m] = fy;
-        own[2 * N + m] = fz;
-        own[3 * N + m] = cx;
-        own[4 * N + m] = cy;
-        own[5 * N + m] = cz;
-      }
-    }
-  }
-  if (MODE == 0) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      Ul += __shfl_xor(Ul, o, 64);
-      Wl += __shfl_xor(Wl, o, 64);
-      npl += __shfl_xor(npl, o, 64);
-    }
-    if (lane == 0) {
-      gpart[2 * a] = Ul;
-      gpart[2 * a + 1] = Wl;
-      gnp[a] = npl;
-    }
-  }
-}
+}  // namespace
 
-// Per-molecule totals: own (hi, lo) plus the j-slot partials of every entry whose j-group holds the
-// molecule, summed in a fixed order (TwoSum-compensated for FP32), written in caller order.
-template <typename T, bool COMP>
-__global__ void k_finalize(const T *__restrict__ own, const T *__restrict__ jpart, int64_t J, int64_t N,
-                           const int32_t *__restrict__ mol_group, const int32_t *__restrict__ g_start,
-                           const int64_t *__restrict__ r_off, const int32_t *__restrict__ r_e,
-                           const int64_t *__restrict__ jb_off, const int32_t *__restrict__ perm, T *__restrict__ out) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= N) return;
-  const int32_t a = mol_group[m];
-  const int32_t p = (int32_t)(m - g_start[a]);
-  T h[3] = {own[m], own[N + m], own[2 * N + m]};
-  T l[3] = {own[3 * N + m], own[4 * N + m], own[5 * N + m]};
-  for (int64_t r = r_off[a]; r < r_off[a + 1]; ++r) {
-    const int64_t k = jb_off[r_e[r]] + p;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const T v = jpart[q * J + k];
-      if (COMP) {
-        T s, err;
-        two_sum(h[q], v, s, err);
-        h[q] = s;
-        l[q] += err;
-      } else {
-        h[q] += v;
-      }
-    }
-  }
-  const int64_t id = perm[m];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) out[3 * id + q] = h[q] + l[q];
-}
+#include "aica_pair.inc"
+
+namespace {
 
 // Fixed-order reduction of per-group partials (deterministic): U, W (FP64) and the pair count.
 __global__ __launch_bounds__(1024) void k_reduce_parts(const double *gpart, const unsigned long long *gnp, int64_t ng,
@@ -804,7 +581,7 @@ static int ensure_groups(aica_dil *h, int64_t n) {
   if (h->groups_ready && h->groups_for_n == n) return AICA_OK;
   auto t0 = std::chrono::steady_clock::now();
   const double density = (double)n / h->geo.total_volume;
-  double target = 13.0;
+  double target = 15.0;
   if (const char *e = getenv("AICA_GROUP_TARGET")) target = std::max(1.0, atof(e));
   int rc = build_groups(h->geo, h->order, h->pairs, density, target, h->grp);
   if (rc) return rc;
@@ -830,8 +607,15 @@ static int ensure_groups(aica_dil *h, int64_t n) {
   if ((rc = upload(h->d_e_B, G.e_B))) return rc;
   if ((rc = upload(h->d_e_vec32, v32))) return rc;
   if ((rc = upload(h->d_e_vec64, v64))) return rc;
-  if ((rc = upload(h->d_r_off, G.r_off))) return rc;
-  if ((rc = upload(h->d_r_e, G.r_e))) return rc;
+  if ((rc = upload(h->d_nl_off, G.nl_off))) return rc;
+  if ((rc = upload(h->d_nl_e, G.nl_e))) return rc;
+  if ((rc = upload(h->d_nl_d, G.nl_d))) return rc;
+  if ((rc = upload(h->d_nl_r, G.nl_r))) return rc;
+  {
+    std::vector<int32_t> rcnt(h->geo.nc);
+    for (int64_t d = 0; d < h->geo.nc; ++d) rcnt[d] = (int32_t)(G.rc_off[d + 1] - G.rc_off[d] + 1);
+    if ((rc = upload(h->d_rcnt, rcnt))) return rc;
+  }
   if ((rc = upload(h->d_orig, G.orig))) return rc;
   h->groups_ready = true;
   h->groups_for_n = n;
@@ -912,14 +696,21 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   if ((rc = h->d_perm.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
   if ((rc = h->d_g_start.ensure(4 * (ng + 1)))) return rc;
   if ((rc = h->d_mol_group.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
-  if ((rc = h->d_jcnt.ensure(4 * std::max<int64_t>(E, 1)))) return rc;
-  if ((rc = h->d_jb_off.ensure(8 * (E + 1)))) return rc;
+  if ((rc = h->d_jcnt.ensure(4 * std::max<int64_t>(nc, 1)))) return rc;
+  if ((rc = h->d_slot_base.ensure(8 * (nc + 1)))) return rc;
+  if ((rc = h->d_cell_sorted.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
   if ((rc = h->d_status.ensure(64))) return rc;
   ProfScope ps(h, "bin", st);
   unsigned long long *status = h->d_status.as<unsigned long long>();
   hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, status, (int64_t)8, 0ull);
   hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(), nc, 0);
   hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_fill.as<int32_t>(), nc, 0);
+  if (h->hint_n != n) {
+    if ((rc = h->d_hint.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
+    hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(std::max<int64_t>(n, 1), 256)), dim3(256), 0, st,
+                       h->d_hint.as<int32_t>(), std::max<int64_t>(n, 1), -1);
+    h->hint_n = n;
+  }
   if (n > 0) {
     if (pos_dtype == AICA_FP64)
       hipLaunchKernelGGL((k_locate<double>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const double *)pos_dev, n,
@@ -927,20 +718,21 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
                          h->d_cf_off.as<int64_t>(), h->d_cf.as<int32_t>(), h->d_cf_sgn.as<int8_t>(), h->d_ccen.as<double>(),
                          h->d_bb.as<double>(), h->d_rank.as<int32_t>(), h->d_gb_off.as<int64_t>(), h->d_gb_cell.as<int32_t>(),
                          h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1], h->gnb[2],
-                         h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status);
+                         h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status, h->d_hint.as<int32_t>());
     else
       hipLaunchKernelGGL((k_locate<float>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const float *)pos_dev, n,
                          h->d_pts.as<double>(), h->d_foff.as<int64_t>(), h->d_fpts.as<int32_t>(), h->d_fcen.as<double>(),
                          h->d_cf_off.as<int64_t>(), h->d_cf.as<int32_t>(), h->d_cf_sgn.as<int8_t>(), h->d_ccen.as<double>(),
                          h->d_bb.as<double>(), h->d_rank.as<int32_t>(), h->d_gb_off.as<int64_t>(), h->d_gb_cell.as<int32_t>(),
                          h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1], h->gnb[2],
-                         h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status);
+                         h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status, h->d_hint.as<int32_t>());
     HIPCHK(hipGetLastError());
   }
   unsigned long long unl = 0;
   HIPCHK(hipMemcpyAsync(&unl, status, 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (unl > 0) return fail(AICA_E_UNLOCATED, std::to_string(unl) + " molecule(s) lie in no mesh cell");
+  hipLaunchKernelGGL(k_max_count, dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(), nc, status);
   if ((rc = scan_exclusive<int32_t>(h, h->d_count.as<int32_t>(), nc, h->d_cell_start.as<int32_t>(), st))) return rc;
   if (n > 0)
     hipLaunchKernelGGL(k_scatter, dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_cell_of.as<int32_t>(), n,
@@ -949,13 +741,21 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
                      h->d_perm.as<int32_t>());
   hipLaunchKernelGGL(k_group_ranges, dim3(grid1d(ng + 1, 256)), dim3(256), 0, st, h->d_cell_start.as<int32_t>(),
                      h->d_g_cell0.as<int32_t>(), ng, h->d_g_start.as<int32_t>(), h->d_mol_group.as<int32_t>());
-  hipLaunchKernelGGL(k_entry_counts, dim3(grid1d(E, 256)), dim3(256), 0, st, h->d_e_B.as<int32_t>(), E,
-                     h->d_g_start.as<int32_t>(), h->d_jcnt.as<int32_t>());
+  hipLaunchKernelGGL(k_slot_counts, dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(),
+                     h->d_rcnt.as<int32_t>(), nc, h->d_jcnt.as<int32_t>());
+  hipLaunchKernelGGL(k_cell_of_sorted, dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_cell_start.as<int32_t>(), nc,
+                     h->d_cell_sorted.as<int32_t>());
   HIPCHK(hipGetLastError());
-  if ((rc = scan_exclusive<int64_t>(h, h->d_jcnt.as<int32_t>(), E, h->d_jb_off.as<int64_t>(), st))) return rc;
+  if ((rc = scan_exclusive<int64_t>(h, h->d_jcnt.as<int32_t>(), nc, h->d_slot_base.as<int64_t>(), st))) return rc;
   int64_t jt = 0;
-  HIPCHK(hipMemcpyAsync(&jt, h->d_jb_off.as<int64_t>() + E, 8, hipMemcpyDeviceToHost, st));
+  unsigned long long over = 0;
+  HIPCHK(hipMemcpyAsync(&jt, h->d_slot_base.as<int64_t>() + nc, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&over, status + 1, 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  if (over > 0)
+    return fail(AICA_E_INVAL, std::to_string(over) + " cell(s) hold more than " + std::to_string(kLCap) +
+                                  " molecules; refine the mesh");
+  if (jt >= (1LL << 31)) return fail(AICA_E_NOMEM, "reaction slots exceed 2^31; split the system");
   h->jtotal = jt;
   h->n = n;
   h->bin_pos = pos_dev;
@@ -993,30 +793,53 @@ static int build_tab(const aica_dil *h, const aica_params *p, LJTab &t) {
   return AICA_OK;
 }
 
+// Reaction buffer: (re)allocate, fill with a pattern no epoch can equal, and advance the epoch.
+static int prepare_jpart(aica_dil *h, size_t bytes, hipStream_t st) {
+  const void *old = h->d_jpart.p;
+  int rc = h->d_jpart.ensure(bytes);
+  if (rc) return rc;
+  if (h->d_jpart.p != old || h->jpart_tagged < h->d_jpart.bytes || h->epoch >= 0x7FFFFFF0u) {
+    const int64_t words = (int64_t)(h->d_jpart.bytes / 4);
+    hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid1d(words, 256)), dim3(256), 0, st, h->d_jpart.as<uint32_t>(),
+                       words, 0xFFFFFFFFu);
+    HIPCHK(hipGetLastError());
+    h->jpart_tagged = h->d_jpart.bytes;
+    h->epoch = 0;
+  }
+  h->epoch += 1;
+  return AICA_OK;
+}
+
 template <typename T, int MODE>
-static int launch_pair(aica_dil *h, const LJTab &tab, bool comp, hipStream_t st, int64_t cap,
+static int launch_pair(aica_dil *h, const LJTab &tab, const AdjTab &at, bool comp, hipStream_t st, int64_t cap,
                        unsigned long long *pcount) {
   using V4 = typename Vec4<T>::type;
   const int64_t ng = h->grp.ng;
   const int64_t nblocks = (ng + kWavesPerBlock - 1) / kWavesPerBlock;
   const int64_t padded = ((nblocks + 7) / 8) * 8;
   const V4 *pos = h->d_pos.as<V4>();
+  const V4 *gs = MODE == 2 ? h->d_gG.as<V4>() : nullptr;
   const V4 *ev = sizeof(T) == 4 ? (const V4 *)h->d_e_vec32.p : (const V4 *)h->d_e_vec64.p;
-  T *jpart = h->d_jpart.as<T>();
-  T *own = h->d_own.as<T>();
-  double *gpart = h->d_gpart.as<double>();
-  unsigned long long *gnp = h->d_gnp.as<unsigned long long>();
+  T *jpart = MODE == 1 ? nullptr : h->d_jpart.as<T>();
+  T *own = MODE == 1 ? nullptr : h->d_own.as<T>();
+  double *gpart = MODE == 0 ? h->d_gpart.as<double>() : (MODE == 2 ? h->d_gpar.as<double>() : nullptr);
+  unsigned long long *gnp = MODE == 0 ? h->d_gnp.as<unsigned long long>() : nullptr;
   int32_t *pairs_out = MODE == 1 ? h->d_pairs.as<int32_t>() : nullptr;
   const int nsp = tab.nsp;
 #define AICA_LAUNCH(MIX, COMP)                                                                                     \
-  hipLaunchKernelGGL((k_pair_fwd<T, MIX, MODE, COMP>), dim3((unsigned)padded), dim3(kBlock), 0, st, pos,          \
-                     h->d_g_start.as<int32_t>(), h->d_e_off.as<int64_t>(), h->d_e_B.as<int32_t>(), ev,             \
-                     h->d_jb_off.as<int64_t>(), jpart, h->jtotal, own, h->n, gpart, gnp, ng, padded, tab,          \
-                     h->d_perm.as<int32_t>(), cap, pairs_out, pcount)
-  if (MODE == 1) {
-    if (nsp == 1) AICA_LAUNCH(0, false);
-    else if (nsp == 2) AICA_LAUNCH(1, false);
-    else AICA_LAUNCH(2, false);
+  hipLaunchKernelGGL((k_pair<T, MIX, MODE, COMP>), dim3((unsigned)padded), dim3(kBlock), 0, st, pos, gs,           \
+                     h->d_g_start.as<int32_t>(), h->d_cell_start.as<int32_t>(), h->d_e_off.as<int64_t>(),          \
+                     h->d_e_B.as<int32_t>(), ev, h->d_slot_base.as<int64_t>(), h->d_cell_sorted.as<int32_t>(),      \
+                     h->d_nl_off.as<int64_t>(), h->d_nl_e.as<int32_t>(), h->d_nl_d.as<int32_t>(),                  \
+                     h->d_nl_r.as<int32_t>(), jpart, h->jtotal, own, h->n, gpart, gnp, ng,                        \
+                     padded, tab, at, h->d_perm.as<int32_t>(), cap, pairs_out, pcount, h->epoch)
+  if constexpr (MODE == 2) {  // the adjoint supports one or two species
+    if (nsp == 1) AICA_LAUNCH(0, true);
+    else AICA_LAUNCH(1, true);
+  } else if (MODE == 1) {
+    if (nsp == 1) AICA_LAUNCH(0, true);
+    else if (nsp == 2) AICA_LAUNCH(1, true);
+    else AICA_LAUNCH(2, true);
   } else if (comp) {
     if (nsp == 1) AICA_LAUNCH(0, true);
     else if (nsp == 2) AICA_LAUNCH(1, true);
@@ -1029,6 +852,15 @@ static int launch_pair(aica_dil *h, const LJTab &tab, bool comp, hipStream_t st,
 #undef AICA_LAUNCH
   HIPCHK(hipGetLastError());
   return AICA_OK;
+}
+
+template <typename T, bool COMP>
+static void launch_finalize(aica_dil *h, void *out, hipStream_t st) {
+  const int64_t n = h->n;
+  hipLaunchKernelGGL((k_finalize<T, COMP>), dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_own.as<T>(),
+                     h->d_jpart.as<T>(), h->jtotal, n, h->d_cell_sorted.as<int32_t>(), h->d_cell_start.as<int32_t>(),
+                     h->d_slot_base.as<int64_t>(), h->d_rcnt.as<int32_t>(), h->d_perm.as<int32_t>(), (T *)out,
+                     h->epoch);
 }
 
 template <typename T>
@@ -1061,27 +893,23 @@ static int forces_impl(aica_dil *h, const void *pos_dev, const int32_t *species,
   const int64_t n = h->n, ng = h->grp.ng, J = h->jtotal;
   int rc;
   if ((rc = gather<T>(h, pos_dev, species, tab.nsp, st))) return rc;
-  if ((rc = h->d_jpart.ensure(sizeof(T) * 3 * std::max<int64_t>(J, 1)))) return rc;
-  if ((rc = h->d_own.ensure(sizeof(T) * 6 * std::max<int64_t>(n, 1)))) return rc;
+  if ((rc = prepare_jpart(h, sizeof(T) * 4 * std::max<int64_t>(J, 1), st))) return rc;
+  if ((rc = h->d_own.ensure(sizeof(T) * 8 * std::max<int64_t>(n, 1)))) return rc;
   if ((rc = h->d_gpart.ensure(sizeof(double) * 2 * std::max<int64_t>(ng, 1)))) return rc;
   if ((rc = h->d_gnp.ensure(8 * std::max<int64_t>(ng, 1)))) return rc;
   {
     ProfScope ps(h, "pair_fwd", st);
-    if ((rc = launch_pair<T, 0>(h, tab, comp, st, 0, nullptr))) return rc;
+    AdjTab at;
+    memset(&at, 0, sizeof at);
+    if ((rc = launch_pair<T, 0>(h, tab, at, comp, st, 0, nullptr))) return rc;
   }
   {
     ProfScope ps(h, "finalize", st);
     if (n > 0 && forces_dev) {
       if (comp && sizeof(T) == 4)
-        hipLaunchKernelGGL((k_finalize<T, true>), dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_own.as<T>(),
-                           h->d_jpart.as<T>(), J, n, h->d_mol_group.as<int32_t>(), h->d_g_start.as<int32_t>(),
-                           h->d_r_off.as<int64_t>(), h->d_r_e.as<int32_t>(), h->d_jb_off.as<int64_t>(),
-                           h->d_perm.as<int32_t>(), (T *)forces_dev);
+        launch_finalize<T, true>(h, forces_dev, st);
       else
-        hipLaunchKernelGGL((k_finalize<T, false>), dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_own.as<T>(),
-                           h->d_jpart.as<T>(), J, n, h->d_mol_group.as<int32_t>(), h->d_g_start.as<int32_t>(),
-                           h->d_r_off.as<int64_t>(), h->d_r_e.as<int32_t>(), h->d_jb_off.as<int64_t>(),
-                           h->d_perm.as<int32_t>(), (T *)forces_dev);
+        launch_finalize<T, false>(h, forces_dev, st);
     }
     if (uw_dev || npairs_dev)
       hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(1024), 0, st, h->d_gpart.as<double>(),
@@ -1115,12 +943,14 @@ int aica_pairs_export(aica_dil *h, const void *pos_dev, const aica_params *param
   if ((rc = h->d_pcount.ensure(64))) return rc;
   unsigned long long *pc = h->d_pcount.as<unsigned long long>();
   hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, pc, (int64_t)1, 0ull);
+  AdjTab at;
+  memset(&at, 0, sizeof at);
   if (params->precision == AICA_FP32) {
     if ((rc = gather<float>(h, pos_dev, nullptr, 1, st))) return rc;
-    if ((rc = launch_pair<float, 1>(h, tab, false, st, cap, pc))) return rc;
+    if ((rc = launch_pair<float, 1>(h, tab, at, false, st, cap, pc))) return rc;
   } else {
     if ((rc = gather<double>(h, pos_dev, nullptr, 1, st))) return rc;
-    if ((rc = launch_pair<double, 1>(h, tab, false, st, cap, pc))) return rc;
+    if ((rc = launch_pair<double, 1>(h, tab, at, false, st, cap, pc))) return rc;
   }
   unsigned long long cnt = 0;
   HIPCHK(hipMemcpyAsync(&cnt, pc, 8, hipMemcpyDeviceToHost, st));
@@ -1230,16 +1060,14 @@ int aica_work_stats(const aica_dil *h, int64_t *dil_candidates, int64_t *lane_pa
   }
   if (lane_pairs) {
     int64_t lp = 0;
+    const Groups &G = h->grp;
     for (int64_t a = 0; a < ng; ++a) {
-      const int64_t ca = (gs[a + 1] - gs[a] + kRow - 1) / kRow;
-      for (int64_t e = h->grp.e_off[a]; e < h->grp.e_off[a + 1]; ++e) {
-        const int64_t B = h->grp.e_B[e];
-        const int64_t cb = (gs[B + 1] - gs[B] + kRow - 1) / kRow;
-        if (e == h->grp.e_off[a])
-          lp += ca * kRow * 8 + (ca * (ca - 1) / 2) * kRow * kRow;  // half tiles + upper chunk pairs
-        else
-          lp += ca * cb * kRow * kRow;
-      }
+      const int64_t na = gs[a + 1] - gs[a];
+      const int64_t ca = (na + kRow - 1) / kRow;
+      lp += ca * kRow * 8 + (ca * (ca - 1) / 2) * kRow * kRow;  // self entry: half tiles + upper chunk pairs
+      int64_t nj = 0;
+      for (int64_t k = G.nl_off[a]; k < G.nl_off[a + 1]; ++k) nj += cs[G.nl_d[k] + 1] - cs[G.nl_d[k]];
+      lp += ca * kRow * kRow * ((nj + kRow - 1) / kRow);  // segments may add a partial chunk each
     }
     *lane_pairs = lp;
   }

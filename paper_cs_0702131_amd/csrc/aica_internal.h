@@ -72,6 +72,15 @@ struct Groups {
   std::vector<int8_t> e_img;    // [E][3] lattice multiples
   std::vector<int64_t> r_off;   // [ng+1] reverse list: entries whose j-group is B
   std::vector<int32_t> r_e;     // entry ids
+  // needed j-cells: for every non-self entry e = (A, B, t), the cells d of B with some cell of A in
+  // range of d + t (CSR by the i-group A, sorted by (e, d))
+  std::vector<int64_t> nl_off;  // [ng+1]
+  std::vector<int32_t> nl_e;    // entry id
+  std::vector<int32_t> nl_d;    // sorted cell id (in group B)
+  std::vector<int32_t> nl_r;    // 1 + rank of the entry in the cell's reverse list (0 is the self entry)
+  // reverse of the needed lists by cell: entries whose needed list holds cell d
+  std::vector<int64_t> rc_off;  // [nc+1]
+  std::vector<int32_t> rc_e;
 };
 
 int build_groups(const Geometry &g, const std::vector<int32_t> &order, const std::vector<CellPair> &pairs,

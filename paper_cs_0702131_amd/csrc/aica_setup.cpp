@@ -702,6 +702,69 @@ int build_groups(const Geometry &g, const std::vector<int32_t> &order, const std
   G.r_e.assign(E, 0);
   std::vector<int64_t> fill(G.r_off.begin(), G.r_off.end() - 1);
   for (int64_t e = 0; e < E; ++e) G.r_e[fill[G.e_B[e]]++] = (int32_t)e;
+
+  // needed j-cells of every non-self entry.  A cell pair (sc, sd, img), sc <= sd, is the physical
+  // pair {cell sc, cell sd + img}; in group terms it is evaluated by entry (A, B, img) with j in sd,
+  // or, for A == B and a negative image, by entry (A, A, -img) with j in sc.
+  std::vector<std::vector<int64_t>> nlists(ng);  // key = entry * 2^31 + j-cell
+  parallel_for(ng, [&](int64_t b, int64_t e, int) {
+    for (int64_t a = b; a < e; ++a) {
+      std::vector<int64_t> &L = nlists[a];
+      const int64_t eb = G.e_off[a], ee = G.e_off[a + 1];
+      auto find_entry = [&](int32_t B, int code) -> int64_t {
+        // entries of A are sorted by (B, code)
+        int64_t lo = eb, hi = ee;
+        const int64_t key = (int64_t)B * 32 + code;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) / 2;
+          const int64_t k = (int64_t)G.e_B[mid] * 32 +
+                            (9 * (G.e_img[3 * mid] + 1) + 3 * (G.e_img[3 * mid + 1] + 1) + (G.e_img[3 * mid + 2] + 1));
+          if (k < key) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+      };
+      for (int64_t p = pstart[a]; p < pstart[a + 1]; ++p) {
+        const CellPair &cp = pairs[p];
+        const int32_t B = G.of_cell[cp.sd];
+        int code = img_code(cp.img[0], cp.img[1], cp.img[2]);
+        int32_t jcell = cp.sd;
+        if (B == a && code == 13) continue;  // inside the self entry
+        if (B == a && code < 13) {
+          code = 26 - code;
+          jcell = cp.sc;
+        }
+        const int64_t en = find_entry(B, code);
+        L.push_back(en * (1LL << 31) + jcell);
+      }
+      std::sort(L.begin(), L.end());
+      L.erase(std::unique(L.begin(), L.end()), L.end());
+    }
+  });
+  G.nl_off.assign(ng + 1, 0);
+  for (int64_t a = 0; a < ng; ++a) G.nl_off[a + 1] = G.nl_off[a] + (int64_t)nlists[a].size();
+  const int64_t NL = G.nl_off[ng];
+  G.nl_e.assign(NL, 0);
+  G.nl_d.assign(NL, 0);
+  G.rc_off.assign(nc + 1, 0);
+  for (int64_t a = 0; a < ng; ++a) {
+    int64_t k = G.nl_off[a];
+    for (int64_t key : nlists[a]) {
+      G.nl_e[k] = (int32_t)(key >> 31);
+      G.nl_d[k] = (int32_t)(key & ((1LL << 31) - 1));
+      G.rc_off[G.nl_d[k] + 1]++;
+      ++k;
+    }
+    std::vector<int64_t>().swap(nlists[a]);
+  }
+  for (int64_t c = 0; c < nc; ++c) G.rc_off[c + 1] += G.rc_off[c];
+  G.rc_e.assign(NL, 0);
+  G.nl_r.assign(NL, 0);
+  std::vector<int64_t> cfill(G.rc_off.begin(), G.rc_off.end() - 1);
+  for (int64_t k = 0; k < NL; ++k) {
+    const int32_t d = G.nl_d[k];
+    G.nl_r[k] = (int32_t)(1 + cfill[d] - G.rc_off[d]);
+    G.rc_e[cfill[d]++] = G.nl_e[k];
+  }
   return AICA_OK;
 }
 
