@@ -141,10 +141,11 @@ def main():
     G32 = torch.tensor(G, dtype=torch.float32, device=dev)
     G64 = torch.tensor(G, dtype=torch.float64, device=dev)
     A.aica_bin(d, x32)
+    A.aica_forces(d, x32, sp, wl.eps, wl.sigma, precision="fp32")
     info = d.info()
     dil_cand, lane_pairs = d.work_stats()
     log(f"groups {info['n_groups']} group pairs {info['n_group_pairs']} ({info['group_seconds']:.1f}s); "
-        f"DIL candidates {dil_cand}, lane pairs {lane_pairs}")
+        f"DIL candidates {dil_cand}, executed lane pairs {lane_pairs}")
 
     res = {}
     t, prof, F32, uw32, npairs = timed_steps(A, d, x32, sp, wl, G32, "fp32", args.steps, args.warmup)
@@ -203,7 +204,8 @@ def main():
            "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
            "config": {"workload": wl.name, "cells": wl.mesh.n_cells, "molecules": wl.n, "npairs": npairs,
                       "step": "aica_bin + aica_forces + aica_forces_adjoint", "parallelism": "single GPU",
-                      "dil_cell_pairs": info["n_dil"], "dil_candidates": dil_cand, "lane_pairs": lane_pairs},
+                      "dil_cell_pairs": info["n_dil"], "dil_candidates": dil_cand, "lane_pairs": lane_pairs,
+                      "lane_efficiency": npairs / max(lane_pairs, 1)},
            "breakdown": breakdown, "errors": errors, "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 

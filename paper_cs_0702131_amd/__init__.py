@@ -67,7 +67,7 @@ class DIL:
         return {k: getattr(inf, k) for k, _ in aica_info._fields_}
 
     def work_stats(self):
-        """(DIL candidate pairs, executed lane-pair evaluations) of the last binning."""
+        """(DIL candidate pairs of the last binning, lane-pair evaluations executed by the last forward call)."""
         a, b = C.c_int64(), C.c_int64()
         check(lib().aica_work_stats(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value

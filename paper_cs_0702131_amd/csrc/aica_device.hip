@@ -87,7 +87,7 @@ struct aica_dil {
   int device = 0;
   bool geometry_on_device = false;
   // device geometry for point location (mesh cell ids)
-  DBuf d_pts, d_foff, d_fpts, d_fcen, d_cf_off, d_cf, d_cf_sgn, d_ccen, d_bb, d_rank;
+  DBuf d_rec_off, d_rec, d_bb;  // point-location cell records and padded boxes, sorted cell order
   DBuf d_gb_off, d_gb_cell;
   double glo[3] = {0, 0, 0}, gh = 1;
   int64_t gnb[3] = {1, 1, 1};
@@ -98,6 +98,7 @@ struct aica_dil {
   DBuf d_orig, d_g_cell0, d_e_off, d_e_B, d_e_vec32, d_e_vec64, d_nl_off, d_nl_e, d_nl_d, d_nl_r, d_rcnt;
   // per step
   bool bin_valid = false;
+  bool wsteps_valid = false;  // d_gnp holds the wave-step counts of a forward call on the current binning
   int64_t n = 0;
   const void *bin_pos = nullptr;
   int32_t bin_dtype = 0;
@@ -105,9 +106,11 @@ struct aica_dil {
   DBuf d_cell_of, d_count, d_cell_start, d_fill, d_perm, d_g_start, d_mol_group, d_jcnt, d_slot_base, d_cell_sorted;
   DBuf d_scan_tmp, d_status, d_hint;
   int64_t hint_n = -1;  // molecule count the hints belong to (-1: none)
+  int64_t perm_n = -1;  // molecule count of the permutation held in d_perm (-1: none)
   // force / adjoint workspace
   DBuf d_pos, d_own, d_jpart, d_gpart, d_gnp, d_gG, d_gpar;
   DBuf d_pairs, d_pcount;
+  DBuf d_red;  // stage-1 rows of the group reductions
   bool profiling = false;
   uint32_t epoch = 0;          // tag of the reaction records written by the current call
   size_t jpart_tagged = 0;     // bytes of d_jpart known to hold no valid tag
@@ -126,59 +129,84 @@ __device__ __forceinline__ double orient3(const double *a, const double *b, cons
   return u0 * (v1 * w2 - v2 * w1) + u1 * (v2 * w0 - v0 * w2) + u2 * (v0 * w1 - v1 * w0);
 }
 
-// Is p inside cell c: some tetrahedron (cell centroid cc, face centroid fc, edge v_k v_k+1) contains p,
-// with a relative tolerance tau of that tetrahedron's volume (tau = 1e-12 for membership; the
-// previous-cell fast path asks for tau = -1e-9, i.e. strictly inside).  The four barycentric tests of
-// tetrahedron k are: the outer face, orient(p, fc, v_k, v_k+1) >= -tol; the edge plane through cc,
-// orient(cc, p, v_k, v_k+1) >= -tol; and the two spoke planes (cc, fc, v_k), (cc, fc, v_k+1), whose
-// orientations s_k = orient(cc, fc, v_k, p) are shared by neighbouring tetrahedra of the fan.
-__device__ bool point_in_cell(const double *p, int32_t c, const double *pts, const int64_t *foff,
-                              const int32_t *fpts, const double *fcen, const int64_t *cf_off, const int32_t *cf,
-                              const int8_t *cf_sgn, const double *ccen, double tau) {
-  const double cc[3] = {ccen[3 * (int64_t)c], ccen[3 * (int64_t)c + 1], ccen[3 * (int64_t)c + 2]};
-  for (int64_t k = cf_off[c]; k < cf_off[c + 1]; ++k) {
-    const int32_t f = cf[k];
-    const double fc[3] = {fcen[3 * (int64_t)f], fcen[3 * (int64_t)f + 1], fcen[3 * (int64_t)f + 2]};
-    const int64_t b0 = foff[f], len = foff[f + 1] - b0;
-    const bool rev = cf_sgn[k] < 0;
-    auto vtx = [&](int64_t j) -> const double * {
-      const int64_t jj = rev ? (len - j) % len : j;  // reversed loop for the neighbour side
-      return pts + 3 * (int64_t)fpts[b0 + jj];
-    };
-    const double *v0 = vtx(0);
-    double s_first = orient3(cc, fc, v0, p), s_prev = s_first;
-    const double *vp = v0;
-    for (int64_t j = 0; j < len; ++j) {
-      const double *vn = vtx(j + 1 == len ? 0 : j + 1);
-      const double s_next = (j + 1 == len) ? s_first : orient3(cc, fc, vn, p);
-      const double v = orient3(cc, fc, vp, vn);
-      const double tol = -tau * fabs(v);
-      if (s_prev >= tol && -s_next >= tol && orient3(p, fc, vp, vn) >= tol && orient3(cc, p, vp, vn) >= tol)
-        return true;
-      s_prev = s_next;
-      vp = vn;
-    }
+// Cell records for point location, one per sorted cell, contiguous:
+//   [nf, cc(3), fc_0(3) .. fc_{nf-1}(3), len_0 .. len_{nf-1}, loop_0(3 len_0) .. loop_{nf-1}(3 len_{nf-1})]
+// with cc the cell's vertex mean, fc the face centroids and each face's vertex loop oriented outward
+// from the cell (counts stored as doubles, exact).
+//
+// Is p inside the cell: some tetrahedron (cc, fc, v_k, v_k+1) contains p, with a relative tolerance tau
+// of that tetrahedron's volume (tau = 1e-12 for membership; the previous-cell fast path asks for
+// tau = -1e-9, i.e. strictly inside).  The four barycentric tests of tetrahedron k are: the outer face,
+// orient(p, fc, v_k, v_k+1) >= -tol; the edge plane through cc, orient(cc, p, v_k, v_k+1) >= -tol; and
+// the two spoke planes (cc, fc, v_k), (cc, fc, v_k+1), whose orientations s_k = orient(cc, fc, v_k, p)
+// are shared by neighbouring tetrahedra of the fan.  The face whose centroid direction from cc best
+// matches p - cc is tried first (the answer does not depend on the order).
+__device__ bool point_in_face_fan(const double *p, const double *cc, const double *fc, const double *V, int len,
+                                  double tau) {
+  double s_first = orient3(cc, fc, V, p), s_prev = s_first;
+  const double *vp = V;
+  for (int j = 0; j < len; ++j) {
+    const double *vn = V + 3 * (j + 1 == len ? 0 : j + 1);
+    const double s_next = (j + 1 == len) ? s_first : orient3(cc, fc, vn, p);
+    const double v = orient3(cc, fc, vp, vn);
+    const double tol = -tau * fabs(v);
+    if (s_prev >= tol && -s_next >= tol && orient3(p, fc, vp, vn) >= tol && orient3(cc, p, vp, vn) >= tol)
+      return true;
+    s_prev = s_next;
+    vp = vn;
   }
   return false;
 }
 
+__device__ bool point_in_rec(const double *p, const double *R, double tau) {
+  const int nf = (int)R[0];
+  const double *cc = R + 1, *FC = R + 4, *LEN = FC + 3 * nf, *V = LEN + nf;
+  const double d0 = p[0] - cc[0], d1 = p[1] - cc[1], d2 = p[2] - cc[2];
+  int best = 0;
+  double bs = -1e300;
+  int64_t boff = 0, off = 0;
+  for (int k = 0; k < nf; ++k) {
+    const double e0 = FC[3 * k] - cc[0], e1 = FC[3 * k + 1] - cc[1], e2 = FC[3 * k + 2] - cc[2];
+    const double sc = (d0 * e0 + d1 * e1 + d2 * e2) / (e0 * e0 + e1 * e1 + e2 * e2);
+    if (sc > bs) {
+      bs = sc;
+      best = k;
+      boff = off;
+    }
+    off += 3 * (int64_t)LEN[k];
+  }
+  if (point_in_face_fan(p, cc, FC + 3 * best, V + boff, (int)LEN[best], tau)) return true;
+  off = 0;
+  for (int k = 0; k < nf; ++k) {
+    const int len = (int)LEN[k];
+    if (k != best && point_in_face_fan(p, cc, FC + 3 * k, V + off, len, tau)) return true;
+    off += 3 * (int64_t)len;
+  }
+  return false;
+}
+
+// Locate each molecule: cell_of[i] = sorted index of the cell that contains x_i.  Molecules are visited
+// in the order trav (the previous binning's sorted order, so that neighbouring threads read neighbouring
+// cell records) or in caller order when trav is null.  Fast path: a molecule strictly inside its previous
+// cell (hint) is in no other cell.  Otherwise every cell whose padded box holds the point is tested in
+// ascending mesh cell id (the lowest containing cell wins a tie on a shared face, edge or vertex).
 template <typename PT>
-__global__ void k_locate(const PT *__restrict__ pos, int64_t n, const double *pts, const int64_t *foff,
-                         const int32_t *fpts, const double *fcen, const int64_t *cf_off, const int32_t *cf,
-                         const int8_t *cf_sgn, const double *ccen, const double *bb, const int32_t *rank,
-                         const int64_t *gb_off, const int32_t *gb_cell, double glo0, double glo1, double glo2,
-                         double gh, int64_t nb0, int64_t nb1, int64_t nb2, int32_t *cell_sorted,
-                         int32_t *count, unsigned long long *status, int32_t *hint) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__global__ void k_locate(const PT *__restrict__ pos, int64_t n, const int32_t *__restrict__ trav,
+                         const int64_t *__restrict__ rec_off, const double *__restrict__ rec,
+                         const double *__restrict__ bb, const int64_t *__restrict__ gb_off,
+                         const int32_t *__restrict__ gb_cell, double glo0, double glo1, double glo2, double gh,
+                         int64_t nb0, int64_t nb1, int64_t nb2, int32_t *__restrict__ cell_of,
+                         int32_t *__restrict__ count, unsigned long long *__restrict__ status,
+                         int32_t *__restrict__ hint) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t i = trav ? trav[t] : t;
   const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
+  const bool finite = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
   int32_t found = -1;
-  // tracking fast path: a molecule strictly inside its previous cell is in no other cell
-  const int32_t h0 = hint ? hint[i] : -1;
-  if (h0 >= 0 && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) &&
-      point_in_cell(p, h0, pts, foff, fpts, fcen, cf_off, cf, cf_sgn, ccen, -1e-9))
-    found = h0;
-  if (found < 0 && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
+  const int32_t h0 = hint[i];
+  if (h0 >= 0 && finite && point_in_rec(p, rec + rec_off[h0], -1e-9)) found = h0;
+  if (found < 0 && finite) {
     const double f0 = floor((p[0] - glo0) / gh), f1 = floor((p[1] - glo1) / gh), f2 = floor((p[2] - glo2) / gh);
     if (f0 >= 0 && f1 >= 0 && f2 >= 0 && f0 < (double)nb0 && f1 < (double)nb1 && f2 < (double)nb2) {
       const int64_t b = (int64_t)f0 + nb0 * ((int64_t)f1 + nb1 * (int64_t)f2);
@@ -186,22 +214,19 @@ __global__ void k_locate(const PT *__restrict__ pos, int64_t n, const double *pt
         const int32_t c = gb_cell[k];
         const double *B = bb + 6 * (int64_t)c;
         if (p[0] < B[0] || p[1] < B[1] || p[2] < B[2] || p[0] > B[3] || p[1] > B[4] || p[2] > B[5]) continue;
-        if (point_in_cell(p, c, pts, foff, fpts, fcen, cf_off, cf, cf_sgn, ccen, 1e-12)) {
+        if (point_in_rec(p, rec + rec_off[c], 1e-12)) {
           found = c;
           break;
         }
       }
     }
   }
-  if (found < 0) {
-    cell_sorted[i] = -1;
+  cell_of[i] = found;
+  if (found < 0)
     atomicAdd(status, 1ull);
-  } else {
-    const int32_t s = rank[found];
-    cell_sorted[i] = s;
-    atomicAdd(&count[s], 1);
-  }
-  if (hint) hint[i] = found;
+  else
+    atomicAdd(&count[found], 1);
+  hint[i] = found;
 }
 
 // ---- exclusive scan of int32 counts into OutT offsets (out[n] = total)
@@ -442,37 +467,81 @@ __device__ __forceinline__ T far_j() { return (T)-1e15; }
 
 namespace {
 
-// Fixed-order reduction of per-group partials (deterministic): U, W (FP64) and the pair count.
-__global__ __launch_bounds__(1024) void k_reduce_parts(const double *gpart, const unsigned long long *gnp, int64_t ng,
-                                                       double *uw, int64_t *npairs) {
-  __shared__ double su[1024], sw[1024];
-  __shared__ unsigned long long sn[1024];
-  double u = 0, w = 0;
-  unsigned long long c = 0;
-  for (int64_t i = threadIdx.x; i < ng; i += 1024) {
-    u += gpart[2 * i];
-    w += gpart[2 * i + 1];
-    c += gnp[i];
-  }
-  su[threadIdx.x] = u;
-  sw[threadIdx.x] = w;
-  sn[threadIdx.x] = c;
+// Deterministic two-stage reduction of per-group partials.  Stage 1: block b sums the fixed row range
+// [b * chunk, (b + 1) * chunk) of a row-major [ng][stride] array (columns col0 .. col0 + K - 1, doubles or
+// unsigned integers read as doubles; integer sums stay exact below 2^53) in a fixed thread order and
+// tree.  Stage 2 (one block) sums the stage-1 rows in block order.
+constexpr int kRedBlocks = 512, kRedThreads = 256;
+
+template <int K, typename S>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_rows(const S *in, int64_t ng, int stride, int col0,
+                                                              int64_t chunk, double *part) {
+  __shared__ double sh[K][kRedThreads];
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = std::min<int64_t>(ng, r0 + chunk);
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += kRedThreads)
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += (double)in[(int64_t)stride * r + col0 + k];
+#pragma unroll
+  for (int k = 0; k < K; ++k) sh[k][threadIdx.x] = acc[k];
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      su[threadIdx.x] += su[threadIdx.x + o];
-      sw[threadIdx.x] += sw[threadIdx.x + o];
-      sn[threadIdx.x] += sn[threadIdx.x + o];
-    }
+  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+#pragma unroll
+      for (int k = 0; k < K; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
     __syncthreads();
   }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) part[(int64_t)K * blockIdx.x + k] = sh[k][0];
+}
+
+// Stage 2 helper: thread 0 ends with the column sums of part[nb][K] in out[K].
+template <int K>
+__device__ void reduce_part_rows(const double *part, int nb, double *out) {
+  __shared__ double sh[K][kRedThreads];
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0;
+  for (int b = threadIdx.x; b < nb; b += kRedThreads)
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += part[(int64_t)K * b + k];
+#pragma unroll
+  for (int k = 0; k < K; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+#pragma unroll
+      for (int k = 0; k < K; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = sh[k][0];
+}
+
+// U, W (FP64) and the pair count from the stage-1 rows (U, W) and (npairs).
+__global__ __launch_bounds__(kRedThreads) void k_reduce_uw(const double *part_uw, const double *part_np, int nb,
+                                                            double *uw, int64_t *npairs) {
+  double a[2], c[1];
+  reduce_part_rows<2>(part_uw, nb, a);
+  __syncthreads();
+  reduce_part_rows<1>(part_np, nb, c);
   if (threadIdx.x == 0) {
     if (uw) {
-      uw[0] = su[0];
-      uw[1] = sw[0];
+      uw[0] = a[0];
+      uw[1] = a[1];
     }
-    if (npairs) npairs[0] = (int64_t)sn[0];
+    if (npairs) npairs[0] = (int64_t)c[0];
   }
+}
+
+inline int red_blocks(int64_t ng, int64_t &chunk) {
+  const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (ng + kRedThreads - 1) / kRedThreads));
+  chunk = (std::max<int64_t>(ng, 1) + nb - 1) / nb;
+  return nb;
 }
 
 inline unsigned grid1d(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
@@ -519,17 +588,46 @@ struct ProfScope {
 static int upload_geometry(aica_dil *h) {
   const Geometry &g = h->geo;
   int rc;
-  if ((rc = upload(h->d_pts, g.pts))) return rc;
-  if ((rc = upload(h->d_foff, g.foff))) return rc;
-  if ((rc = upload(h->d_fpts, g.fpts))) return rc;
-  if ((rc = upload(h->d_fcen, g.fcen))) return rc;
-  if ((rc = upload(h->d_cf_off, g.cf_off))) return rc;
-  if ((rc = upload(h->d_cf, g.cf))) return rc;
-  if ((rc = upload(h->d_cf_sgn, g.cf_sgn))) return rc;
-  if ((rc = upload(h->d_ccen, g.ccen))) return rc;
-  if ((rc = upload(h->d_rank, h->rank))) return rc;
-  // padded bounding boxes and the point-location grid (cells listed in every bin their box touches,
-  // ascending cell id so the lowest containing cell is found first)
+  // cell records for point location, in sorted cell order (layout described at point_in_rec)
+  {
+    std::vector<int64_t> roff(g.nc + 1, 0);
+    for (int64_t s = 0; s < g.nc; ++s) {
+      const int64_t c = h->order[s];
+      int64_t sz = 4;
+      for (int64_t k = g.cf_off[c]; k < g.cf_off[c + 1]; ++k) {
+        const int32_t f = g.cf[k];
+        sz += 4 + 3 * (g.foff[f + 1] - g.foff[f]);
+      }
+      roff[s + 1] = roff[s] + sz;
+    }
+    std::vector<double> rec(roff[g.nc]);
+    parallel_for(g.nc, [&](int64_t s0, int64_t s1, int) {
+      for (int64_t s = s0; s < s1; ++s) {
+        const int64_t c = h->order[s];
+        const int64_t nf = g.cf_off[c + 1] - g.cf_off[c];
+        double *R = rec.data() + roff[s];
+        R[0] = (double)nf;
+        for (int q = 0; q < 3; ++q) R[1 + q] = g.ccen[3 * c + q];
+        double *FC = R + 4, *LEN = FC + 3 * nf, *V = LEN + nf;
+        for (int64_t k = 0; k < nf; ++k) {
+          const int32_t f = g.cf[g.cf_off[c] + k];
+          const int64_t b0 = g.foff[f], len = g.foff[f + 1] - b0;
+          const bool rev = g.cf_sgn[g.cf_off[c] + k] < 0;  // the neighbour side walks the loop backwards
+          for (int q = 0; q < 3; ++q) FC[3 * k + q] = g.fcen[3 * (int64_t)f + q];
+          LEN[k] = (double)len;
+          for (int64_t j = 0; j < len; ++j) {
+            const int64_t jj = rev ? (len - j) % len : j;
+            for (int q = 0; q < 3; ++q) V[3 * j + q] = g.pts[3 * (int64_t)g.fpts[b0 + jj] + q];
+          }
+          V += 3 * len;
+        }
+      }
+    });
+    if ((rc = upload(h->d_rec_off, roff))) return rc;
+    if ((rc = upload(h->d_rec, rec))) return rc;
+  }
+  // padded bounding boxes (sorted cell order) and the point-location grid (sorted cell indices listed in
+  // every bin their box touches, in ascending mesh cell id so the lowest containing cell is found first)
   std::vector<double> bb(6 * g.nc);
   for (int64_t c = 0; c < g.nc; ++c)
     for (int q = 0; q < 3; ++q) {
@@ -537,7 +635,12 @@ static int upload_geometry(aica_dil *h) {
       bb[6 * c + q] = g.lo[3 * c + q] - 1e-9 * ext;
       bb[6 * c + 3 + q] = g.hi[3 * c + q] + 1e-9 * ext;
     }
-  if ((rc = upload(h->d_bb, bb))) return rc;
+  {
+    std::vector<double> bbs(6 * g.nc);
+    for (int64_t s = 0; s < g.nc; ++s)
+      for (int q = 0; q < 6; ++q) bbs[6 * s + q] = bb[6 * (int64_t)h->order[s] + q];
+    if ((rc = upload(h->d_bb, bbs))) return rc;
+  }
   double gh = std::cbrt(g.total_volume / (double)g.nc);
   for (int q = 0; q < 3; ++q) gh = std::max(gh, (g.dom_hi[q] - g.dom_lo[q]) / 2048.0);
   int64_t nb[3];
@@ -570,7 +673,7 @@ static int upload_geometry(aica_dil *h) {
     for (int q = 0; q < 3; ++q) range(c, q, lo[q], hi[q]);
     for (int64_t z = lo[2]; z <= hi[2]; ++z)
       for (int64_t y = lo[1]; y <= hi[1]; ++y)
-        for (int64_t x = lo[0]; x <= hi[0]; ++x) cells[fill[x + nb[0] * (y + nb[1] * z)]++] = (int32_t)c;
+        for (int64_t x = lo[0]; x <= hi[0]; ++x) cells[fill[x + nb[0] * (y + nb[1] * z)]++] = h->rank[c];
   }
   if ((rc = upload(h->d_gb_off, off))) return rc;
   if ((rc = upload(h->d_gb_cell, cells))) return rc;
@@ -674,6 +777,7 @@ void aica_dil_free(aica_dil *h) {
 int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, void *hip_stream) {
   if (!h) return fail(AICA_E_INVAL, "handle is NULL");
   h->bin_valid = false;
+  h->wsteps_valid = false;
   if (n < 0 || (n > 0 && !pos_dev)) return fail(AICA_E_INVAL, "bad positions");
   if (n >= (1LL << 31)) return fail(AICA_E_INVAL, "too many molecules for int32 ids");
   if (pos_dtype != AICA_FP32 && pos_dtype != AICA_FP64) return fail(AICA_E_INVAL, "pos_dtype must be AICA_FP32 or AICA_FP64");
@@ -712,20 +816,19 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
     h->hint_n = n;
   }
   if (n > 0) {
+    // visit molecules in the previous binning's sorted order when there is one for this n
+    const int32_t *trav = h->perm_n == n ? h->d_perm.as<int32_t>() : nullptr;
+#define AICA_LOCATE(PT)                                                                                            \
+  hipLaunchKernelGGL((k_locate<PT>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const PT *)pos_dev, n, trav,          \
+                     h->d_rec_off.as<int64_t>(), h->d_rec.as<double>(), h->d_bb.as<double>(),                      \
+                     h->d_gb_off.as<int64_t>(), h->d_gb_cell.as<int32_t>(), h->glo[0], h->glo[1], h->glo[2], h->gh, \
+                     h->gnb[0], h->gnb[1], h->gnb[2], h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status, \
+                     h->d_hint.as<int32_t>())
     if (pos_dtype == AICA_FP64)
-      hipLaunchKernelGGL((k_locate<double>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const double *)pos_dev, n,
-                         h->d_pts.as<double>(), h->d_foff.as<int64_t>(), h->d_fpts.as<int32_t>(), h->d_fcen.as<double>(),
-                         h->d_cf_off.as<int64_t>(), h->d_cf.as<int32_t>(), h->d_cf_sgn.as<int8_t>(), h->d_ccen.as<double>(),
-                         h->d_bb.as<double>(), h->d_rank.as<int32_t>(), h->d_gb_off.as<int64_t>(), h->d_gb_cell.as<int32_t>(),
-                         h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1], h->gnb[2],
-                         h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status, h->d_hint.as<int32_t>());
+      AICA_LOCATE(double);
     else
-      hipLaunchKernelGGL((k_locate<float>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const float *)pos_dev, n,
-                         h->d_pts.as<double>(), h->d_foff.as<int64_t>(), h->d_fpts.as<int32_t>(), h->d_fcen.as<double>(),
-                         h->d_cf_off.as<int64_t>(), h->d_cf.as<int32_t>(), h->d_cf_sgn.as<int8_t>(), h->d_ccen.as<double>(),
-                         h->d_bb.as<double>(), h->d_rank.as<int32_t>(), h->d_gb_off.as<int64_t>(), h->d_gb_cell.as<int32_t>(),
-                         h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1], h->gnb[2],
-                         h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status, h->d_hint.as<int32_t>());
+      AICA_LOCATE(float);
+#undef AICA_LOCATE
     HIPCHK(hipGetLastError());
   }
   unsigned long long unl = 0;
@@ -734,6 +837,7 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   if (unl > 0) return fail(AICA_E_UNLOCATED, std::to_string(unl) + " molecule(s) lie in no mesh cell");
   hipLaunchKernelGGL(k_max_count, dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(), nc, status);
   if ((rc = scan_exclusive<int32_t>(h, h->d_count.as<int32_t>(), nc, h->d_cell_start.as<int32_t>(), st))) return rc;
+  h->perm_n = -1;
   if (n > 0)
     hipLaunchKernelGGL(k_scatter, dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_cell_of.as<int32_t>(), n,
                        h->d_cell_start.as<int32_t>(), h->d_fill.as<int32_t>(), h->d_perm.as<int32_t>());
@@ -756,6 +860,7 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
     return fail(AICA_E_INVAL, std::to_string(over) + " cell(s) hold more than " + std::to_string(kLCap) +
                                   " molecules; refine the mesh");
   if (jt >= (1LL << 31)) return fail(AICA_E_NOMEM, "reaction slots exceed 2^31; split the system");
+  h->perm_n = n;  // d_perm holds this binning's permutation
   h->jtotal = jt;
   h->n = n;
   h->bin_pos = pos_dev;
@@ -896,12 +1001,14 @@ static int forces_impl(aica_dil *h, const void *pos_dev, const int32_t *species,
   if ((rc = prepare_jpart(h, sizeof(T) * 4 * std::max<int64_t>(J, 1), st))) return rc;
   if ((rc = h->d_own.ensure(sizeof(T) * 8 * std::max<int64_t>(n, 1)))) return rc;
   if ((rc = h->d_gpart.ensure(sizeof(double) * 2 * std::max<int64_t>(ng, 1)))) return rc;
-  if ((rc = h->d_gnp.ensure(8 * std::max<int64_t>(ng, 1)))) return rc;
+  if ((rc = h->d_gnp.ensure(16 * std::max<int64_t>(ng, 1)))) return rc;
+  if ((rc = h->d_red.ensure(sizeof(double) * 8 * kRedBlocks))) return rc;
   {
     ProfScope ps(h, "pair_fwd", st);
     AdjTab at;
     memset(&at, 0, sizeof at);
     if ((rc = launch_pair<T, 0>(h, tab, at, comp, st, 0, nullptr))) return rc;
+    h->wsteps_valid = true;
   }
   {
     ProfScope ps(h, "finalize", st);
@@ -911,9 +1018,16 @@ static int forces_impl(aica_dil *h, const void *pos_dev, const int32_t *species,
       else
         launch_finalize<T, false>(h, forces_dev, st);
     }
-    if (uw_dev || npairs_dev)
-      hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(1024), 0, st, h->d_gpart.as<double>(),
-                         h->d_gnp.as<unsigned long long>(), ng, uw_dev, npairs_dev);
+    if (uw_dev || npairs_dev) {
+      int64_t chunk;
+      const int nb = red_blocks(ng, chunk);
+      double *pu = h->d_red.as<double>(), *pn = pu + 2 * kRedBlocks;
+      hipLaunchKernelGGL((k_reduce_rows<2, double>), dim3(nb), dim3(kRedThreads), 0, st, h->d_gpart.as<double>(), ng,
+                         2, 0, chunk, pu);
+      hipLaunchKernelGGL((k_reduce_rows<1, unsigned long long>), dim3(nb), dim3(kRedThreads), 0, st,
+                         h->d_gnp.as<unsigned long long>(), ng, 2, 0, chunk, pn);
+      hipLaunchKernelGGL(k_reduce_uw, dim3(1), dim3(kRedThreads), 0, st, pu, pn, nb, uw_dev, npairs_dev);
+    }
     HIPCHK(hipGetLastError());
   }
   return AICA_OK;
@@ -1059,16 +1173,12 @@ int aica_work_stats(const aica_dil *h, int64_t *dil_candidates, int64_t *lane_pa
     *dil_candidates = cand;
   }
   if (lane_pairs) {
+    // wave-steps counted by the last forward pair kernel, 64 lane-pair evaluations each
+    if (!h->wsteps_valid) return fail(AICA_E_INVAL, "aica_forces must run after aica_bin first");
+    std::vector<unsigned long long> gn(2 * ng);
+    HIPCHK(hipMemcpy(gn.data(), h->d_gnp.p, 16 * ng, hipMemcpyDeviceToHost));
     int64_t lp = 0;
-    const Groups &G = h->grp;
-    for (int64_t a = 0; a < ng; ++a) {
-      const int64_t na = gs[a + 1] - gs[a];
-      const int64_t ca = (na + kRow - 1) / kRow;
-      lp += ca * kRow * 8 + (ca * (ca - 1) / 2) * kRow * kRow;  // self entry: half tiles + upper chunk pairs
-      int64_t nj = 0;
-      for (int64_t k = G.nl_off[a]; k < G.nl_off[a + 1]; ++k) nj += cs[G.nl_d[k] + 1] - cs[G.nl_d[k]];
-      lp += ca * kRow * kRow * ((nj + kRow - 1) / kRow);  // segments may add a partial chunk each
-    }
+    for (int64_t a = 0; a < ng; ++a) lp += 64 * (int64_t)gn[2 * a + 1];
     *lane_pairs = lp;
   }
   return AICA_OK;

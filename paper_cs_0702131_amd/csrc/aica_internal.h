@@ -1,8 +1,11 @@
 // Internal declarations shared by the host setup code and the HIP launchers.
 #pragma once
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "aica.h"
@@ -15,6 +18,28 @@ int fail(int code, const std::string &msg);
 
 // Number of host worker threads for setup (AICA_THREADS, else OMP_NUM_THREADS, else hardware).
 int host_threads();
+
+// f(begin, end, worker) over [0, n) in dynamically claimed chunks on host_threads() threads.
+template <class F>
+void parallel_for(int64_t n, F f) {
+  const int nt = host_threads();
+  if (n < 1024 || nt == 1) {
+    f(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  std::atomic<int64_t> next(0);
+  const int64_t chunk = std::max<int64_t>(64, n / (nt * 16));
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t]() {
+      for (;;) {
+        const int64_t b = next.fetch_add(chunk);
+        if (b >= n) break;
+        f(b, std::min(n, b + chunk), t);
+      }
+    });
+  for (auto &x : th) x.join();
+}
 
 // Host copy of the mesh plus derived cell geometry (Sec. 2.3: static mesh).
 struct Geometry {

@@ -32,26 +32,6 @@ int host_threads() {
   return std::min(n, 64);
 }
 
-template <class F>
-static void parallel_for(int64_t n, F f) {
-  int nt = host_threads();
-  if (n < 1024 || nt == 1) {
-    f(0, n, 0);
-    return;
-  }
-  std::vector<std::thread> th;
-  std::atomic<int64_t> next(0);
-  const int64_t chunk = std::max<int64_t>(64, n / (nt * 16));
-  for (int t = 0; t < nt; ++t)
-    th.emplace_back([&, t]() {
-      for (;;) {
-        int64_t b = next.fetch_add(chunk);
-        if (b >= n) break;
-        f(b, std::min(n, b + chunk), t);
-      }
-    });
-  for (auto &x : th) x.join();
-}
 
 // ------------------------------------------------------------------ small vector helpers
 
