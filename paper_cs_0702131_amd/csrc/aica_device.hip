@@ -684,7 +684,7 @@ static int ensure_groups(aica_dil *h, int64_t n) {
   if (h->groups_ready && h->groups_for_n == n) return AICA_OK;
   auto t0 = std::chrono::steady_clock::now();
   const double density = (double)n / h->geo.total_volume;
-  double target = 15.0;
+  double target = 24.0;
   if (const char *e = getenv("AICA_GROUP_TARGET")) target = std::max(1.0, atof(e));
   int rc = build_groups(h->geo, h->order, h->pairs, density, target, h->grp);
   if (rc) return rc;
@@ -779,7 +779,7 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   h->bin_valid = false;
   h->wsteps_valid = false;
   if (n < 0 || (n > 0 && !pos_dev)) return fail(AICA_E_INVAL, "bad positions");
-  if (n >= (1LL << 31)) return fail(AICA_E_INVAL, "too many molecules for int32 ids");
+  if (n >= (1LL << 28) - 1) return fail(AICA_E_INVAL, "too many molecules (the pair kernels take fewer than 2^28 - 1)");
   if (pos_dtype != AICA_FP32 && pos_dtype != AICA_FP64) return fail(AICA_E_INVAL, "pos_dtype must be AICA_FP32 or AICA_FP64");
   hipStream_t st = (hipStream_t)hip_stream;
   int rc;
@@ -920,7 +920,8 @@ static int launch_pair(aica_dil *h, const LJTab &tab, const AdjTab &at, bool com
                        unsigned long long *pcount) {
   using V4 = typename Vec4<T>::type;
   const int64_t ng = h->grp.ng;
-  const int64_t nblocks = (ng + kWavesPerBlock - 1) / kWavesPerBlock;
+  constexpr int NW = pair_waves(sizeof(T));
+  const int64_t nblocks = (ng + NW - 1) / NW;
   const int64_t padded = ((nblocks + 7) / 8) * 8;
   const V4 *pos = h->d_pos.as<V4>();
   const V4 *gs = MODE == 2 ? h->d_gG.as<V4>() : nullptr;
@@ -932,12 +933,11 @@ static int launch_pair(aica_dil *h, const LJTab &tab, const AdjTab &at, bool com
   int32_t *pairs_out = MODE == 1 ? h->d_pairs.as<int32_t>() : nullptr;
   const int nsp = tab.nsp;
 #define AICA_LAUNCH(MIX, COMP)                                                                                     \
-  hipLaunchKernelGGL((k_pair<T, MIX, MODE, COMP>), dim3((unsigned)padded), dim3(kBlock), 0, st, pos, gs,           \
-                     h->d_g_start.as<int32_t>(), h->d_cell_start.as<int32_t>(), h->d_e_off.as<int64_t>(),          \
-                     h->d_e_B.as<int32_t>(), ev, h->d_slot_base.as<int64_t>(), h->d_cell_sorted.as<int32_t>(),      \
-                     h->d_nl_off.as<int64_t>(), h->d_nl_e.as<int32_t>(), h->d_nl_d.as<int32_t>(),                  \
-                     h->d_nl_r.as<int32_t>(), jpart, h->jtotal, own, h->n, gpart, gnp, ng,                        \
-                     padded, tab, at, h->d_perm.as<int32_t>(), cap, pairs_out, pcount, h->epoch)
+  hipLaunchKernelGGL((k_pair<T, MIX, MODE, COMP>), dim3((unsigned)padded), dim3(64 * NW), 0, st, pos, gs,          \
+                     h->d_g_start.as<int32_t>(), h->d_g_cell0.as<int32_t>(), h->d_cell_start.as<int32_t>(), ev,    \
+                     h->d_slot_base.as<int64_t>(), h->d_nl_off.as<int64_t>(), h->d_nl_e.as<int32_t>(),            \
+                     h->d_nl_d.as<int32_t>(), h->d_nl_r.as<int32_t>(), jpart, own, gpart, gnp, ng, padded, tab, at, \
+                     h->d_perm.as<int32_t>(), cap, pairs_out, pcount, h->epoch)
   if constexpr (MODE == 2) {  // the adjoint supports one or two species
     if (nsp == 1) AICA_LAUNCH(0, true);
     else AICA_LAUNCH(1, true);

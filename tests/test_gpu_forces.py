@@ -91,8 +91,8 @@ def test_small_random_both_precisions(A, oracle, seed, periodic, species):
 
 
 def test_dense_coarse_mesh_many_chunks(A, oracle):
-    # 2x2x2 cells of 4.2 sigma at density ~0.8: ~60 molecules per cell, several 16-lane chunks
-    # per group and a ragged tail in every tile dimension
+    # 2x2x2 cells of 4.2 sigma at density ~0.8: ~60 molecules per cell, so groups of more than 64
+    # molecules (several i-passes), j-lists of several segments and ragged tails everywhere
     wl = W.small_random(n_mesh=(2, 2, 2), L=(8.4, 8.4, 8.4), N=470, seed=8, min_sep=0.85, species_frac=0.8)
     check_case(A, oracle, wl, "fp64", 1e-12, 1e-12)
     check_case(A, oracle, wl, "fp32", 1e-5, 1e-6)
