@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -423,15 +424,26 @@ template <typename T, int MIX>
 struct LaneLJ {
   T s0, s1, g0, g1, u0, u1;
   int ti;
+  // One or two species: the parameters are selected from kernel-argument values (no per-lane
+  // memory access, which would otherwise be waited for inside the pair loops).
   __device__ __forceinline__ void init(const LJTab &t, int ti_) {
     ti = ti_;
-    s0 = tab_sig2<T>(t, ti * 8);
-    g0 = tab_e24<T>(t, ti * 8);
-    u0 = tab_e4<T>(t, ti * 8);
-    if (MIX >= 1) {
-      s1 = tab_sig2<T>(t, ti * 8 + 1);
-      g1 = tab_e24<T>(t, ti * 8 + 1);
-      u1 = tab_e4<T>(t, ti * 8 + 1);
+    if (MIX == 0) {
+      s0 = tab_sig2<T>(t, 0);
+      g0 = tab_e24<T>(t, 0);
+      u0 = tab_e4<T>(t, 0);
+    } else if (MIX == 1) {
+      const bool b = ti != 0;
+      s0 = b ? tab_sig2<T>(t, 8) : tab_sig2<T>(t, 0);
+      g0 = b ? tab_e24<T>(t, 8) : tab_e24<T>(t, 0);
+      u0 = b ? tab_e4<T>(t, 8) : tab_e4<T>(t, 0);
+      s1 = b ? tab_sig2<T>(t, 9) : tab_sig2<T>(t, 1);
+      g1 = b ? tab_e24<T>(t, 9) : tab_e24<T>(t, 1);
+      u1 = b ? tab_e4<T>(t, 9) : tab_e4<T>(t, 1);
+    } else {
+      s0 = tab_sig2<T>(t, ti * 8);
+      g0 = tab_e24<T>(t, ti * 8);
+      u0 = tab_e4<T>(t, ti * 8);
     }
   }
   __device__ __forceinline__ void get(const LJTab &t, int tj, T &sig2, T &e24, T &e4) const {

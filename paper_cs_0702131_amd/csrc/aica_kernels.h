@@ -46,11 +46,12 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks_padded
   return (bid & 7) * per + (bid >> 3);
 }
 
-// Make LDS writes of this wave visible to its own later LDS reads.
+// Order this wave's LDS accesses across this point.  The LDS performs one wave's operations in issue
+// order, so a later read (by any lane) sees an earlier write; only the compiler must not move memory
+// accesses across.  (A memory fence here would also wait for outstanding global stores.)
 __device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  asm volatile("" ::: "memory");
 }
 
 }  // namespace aica
