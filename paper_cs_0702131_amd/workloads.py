@@ -479,3 +479,38 @@ def small_random(n_mesh=(3, 3, 3), L=(8.0, 8.0, 8.0), N=200, periodic_axes=(0, 1
         sp = binary_species(N, species_frac, _rng(seed, 2))
         eps, sig = np.array([1.0, 0.5]), np.array([1.0, 0.88])
     return Workload("small_random", mesh, x, sp, eps, sig, 2.5, lo, hi, tuple(periodic_axes))
+
+
+def cutoff_band_pairs(n_side=6, spacing=8.0, seed=21):
+    """Isolated molecule pairs whose separations d are multiples of Q with |d|^2 within a few FP32
+    ulps of rc^2 = 6.25 on both sides (and one pair at exactly rc), on a jittered periodic hex mesh.
+    Pairs from different sites are farther apart than rc, so each site holds at most one interacting
+    pair; whether it interacts is decided by the exact integer sum a^2 + b^2 + c^2 < (2.5 / Q)^2."""
+    rng = _rng(seed, 0)
+    R = int(round(2.5 / Q)) ** 2
+    L = float(qround(n_side * spacing))
+    xi, xj = [], []
+    for s in range(n_side ** 3):
+        site = np.array([s % n_side, (s // n_side) % n_side, s // n_side ** 2], dtype=np.float64) * spacing
+        base = qround(site + rng.uniform(0.5, 1.5, size=3))
+        if s == 0:
+            abc = np.array([int(round(2.5 / Q)), 0, 0])
+        else:
+            # aim at R + k; of 256 random (a, b), keep the triple closest to the aim
+            k = int(rng.integers(-4000, 4001))
+            ab = rng.integers(0, 52000, size=(256, 2)).astype(np.int64)
+            rest = R + k - (ab ** 2).sum(1)
+            c = np.floor(np.sqrt(rest.astype(np.float64))).astype(np.int64)
+            c += ((c + 1) ** 2 <= rest).astype(np.int64) - (c ** 2 > rest).astype(np.int64)
+            best = int(np.argmin(rest - c ** 2))
+            abc = np.array([ab[best, 0], ab[best, 1], c[best]]) * rng.choice([-1, 1], size=3)
+        xi.append(base)
+        xj.append(base + abc * Q)
+    x = np.vstack([np.array(xi), np.array(xj)])
+    x = np.mod(x, L)
+    nodes = uniform_nodes(L, 2 * n_side)
+    mesh = jitter_interior(hex_mesh(nodes, nodes, nodes, periodic_axes=(0, 1, 2)), nodes, nodes, nodes, 0.2,
+                           _rng(seed, 1))
+    n = len(x)
+    return Workload(f"cutoff_band_{n}", mesh, qround(x), np.zeros(n, np.int32), np.array([1.0]), np.array([1.0]),
+                    2.5, np.zeros(3), np.full(3, L), (0, 1, 2))

@@ -90,6 +90,24 @@ def test_small_random_both_precisions(A, oracle, seed, periodic, species):
     check_case(A, oracle, wl, "fp32", 1e-5, 1e-6)
 
 
+def test_cutoff_band_pairs(A, oracle):
+    # separations within a few FP32 ulps of rc^2 on both sides (and exactly rc): the FP32 path must
+    # reproduce the exact pair set, including pairs where a plain FP32 evaluation of s decides wrongly
+    wl = W.cutoff_band_pairs()
+    n = wl.n // 2
+    d = wl.x[n:] - wl.x[:n]
+    d -= wl.box_hi[0] * np.round(d / wl.box_hi[0])
+    m = np.round(d / W.Q).astype(np.int64)
+    exact_in = (m ** 2).sum(1) < int(round(2.5 / W.Q)) ** 2
+    d32 = d.astype(np.float32)
+    t = np.float32(d32[:, 2].astype(np.float64) ** 2)  # fmaf(dx, dx, fmaf(dy, dy, dz * dz))
+    t = np.float32(d32[:, 1].astype(np.float64) ** 2 + t)
+    s32 = np.float32(d32[:, 0].astype(np.float64) ** 2 + t)
+    assert ((s32 < np.float32(6.25)) != exact_in).sum() > 0
+    for prec in ("fp32", "fp64"):
+        check_case(A, oracle, wl, prec, 1e-5 if prec == "fp32" else 1e-12, 1e-5 if prec == "fp32" else 1e-12)
+
+
 def test_dense_coarse_mesh_many_chunks(A, oracle):
     # 2x2x2 cells of 4.2 sigma at density ~0.8: ~60 molecules per cell, so groups of more than 64
     # molecules (several i-passes), j-lists of several segments and ragged tails everywhere
