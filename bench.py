@@ -50,6 +50,40 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+# Kernel sources whose digest ties the traffic counters to the code they were measured on.
+KERNEL_SOURCES = ["aica_pair.inc", "aica_device.hip", "aica_kernels.h", "aica_adjoint.inc"]
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_cs_0702131_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the copy-kernel calibration), or None when
+    the summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    rows = {}
+    digest = None
+    with open(path) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) >= 2 and f[0] == "sources_sha256:":
+                digest = f[1]
+            if len(f) == 6 and f[0] == "traffic:":
+                rows[f[1]] = float(f[2]) * 1024 * float(f[3]) + float(f[4]) * 1024 * float(f[5])
+    if digest != kernel_digest():
+        return None
+    return rows.get(kernel)
+
+
 def timed_steps(A, d, x, sp, wl, G, precision, steps, warmup, adjoint=True):
     import torch
     st = torch.cuda.current_stream()
@@ -113,7 +147,20 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (calibrates the FETCH_SIZE and "
+                         "WRITE_SIZE counters against a kernel of known traffic) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs (processor referral "
                                    "and halo exchange) are not part of it", "n_gpus": args.gpus}))
@@ -179,8 +226,10 @@ def main():
     else:
         kname, kms, flops = "pair_fwd", fwd_ms, FLOP_FWD_PAIR * npairs + FLOP_REJECT * rejected
     achieved = flops / (kms * 1e-3) / 1e12
+    traffic = measured_traffic(kname, args.workload)
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None, "kernel": kname,
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic, "traffic_unit": "bytes per launch",
+                "kernel": kname,
                 "kernel_ms": kms, "algorithmic_flop": flops}
 
     cpu = None
