@@ -89,6 +89,8 @@ struct aica_dil {
   bool geometry_on_device = false;
   // device geometry for point location (mesh cell ids)
   DBuf d_rec_off, d_rec, d_bb;  // point-location cell records and padded boxes, sorted cell order
+  DBuf d_rec32;                 // FP32 records for the previous-cell test (cells of at most kR32 float4)
+  bool has_rec32 = false;
   DBuf d_gb_off, d_gb_cell;
   double glo[3] = {0, 0, 0}, gh = 1;
   int64_t gnb[3] = {1, 1, 1};
@@ -105,7 +107,7 @@ struct aica_dil {
   int32_t bin_dtype = 0;
   int64_t jtotal = 0;
   DBuf d_cell_of, d_count, d_cell_start, d_fill, d_perm, d_g_start, d_mol_group, d_jcnt, d_slot_base, d_cell_sorted;
-  DBuf d_scan_tmp, d_status, d_hint;
+  DBuf d_scan_tmp, d_status, d_hint, d_slow;
   int64_t hint_n = -1;  // molecule count the hints belong to (-1: none)
   int64_t perm_n = -1;  // molecule count of the permutation held in d_perm (-1: none)
   // force / adjoint workspace
@@ -186,22 +188,112 @@ __device__ bool point_in_rec(const double *p, const double *R, double tau) {
   return false;
 }
 
-// Locate each molecule: cell_of[i] = sorted index of the cell that contains x_i.  Molecules are visited
-// in the order trav (the previous binning's sorted order, so that neighbouring threads read neighbouring
-// cell records) or in caller order when trav is null.  Fast path: a molecule strictly inside its previous
-// cell (hint) is in no other cell.  Otherwise every cell whose padded box holds the point is tested in
-// ascending mesh cell id (the lowest containing cell wins a tie on a shared face, edge or vertex).
+// FP32 copies of the cell records for the previous-cell test, fixed stride kR32 float4 per sorted cell:
+//   [0] (nf, a.x, a.y, a.z) with a the FP32-rounded vertex mean; [1] (cc - a, 0);
+//   [2 .. 2 + nf) (fc_k - a, len_k); then the face loops, one vertex (v - a, 0) per float4.
+// A point is accepted when some tetrahedron contains it with every orientation above 1e-4 of that
+// tetrahedron's own (FP32) orientation.  The FP32 rounding of the records and of the orientations is
+// below 1e-5 of that scale, so an accepted point is strictly inside in exact arithmetic too (the FP64
+// test with tau = -1e-9 accepts it); anything else goes to the FP64 test.
+constexpr int kR32 = 32;
+
+__device__ __forceinline__ float orient3f(const float *a, const float *b, const float *c, const float *d) {
+  const float u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
+  const float v0 = c[0] - a[0], v1 = c[1] - a[1], v2 = c[2] - a[2];
+  const float w0 = d[0] - a[0], w1 = d[1] - a[1], w2 = d[2] - a[2];
+  return u0 * (v1 * w2 - v2 * w1) + u1 * (v2 * w0 - v0 * w2) + u2 * (v0 * w1 - v1 * w0);
+}
+
+__device__ bool surely_in_rec32(const double *p, const float4 *R) {
+  const float4 h = R[0], h2 = R[1];
+  const int nf = (int)h.x;
+  const float pr[3] = {(float)(p[0] - (double)h.y), (float)(p[1] - (double)h.z), (float)(p[2] - (double)h.w)};
+  const float cc[3] = {h2.x, h2.y, h2.z};
+  // best face first (the answer does not depend on the order)
+  int best = 0, boff = 0, off = 0;
+  float bs = -3.0e38f;
+  for (int k = 0; k < nf; ++k) {
+    const float4 f = R[2 + k];
+    const float e0 = f.x - cc[0], e1 = f.y - cc[1], e2 = f.z - cc[2];
+    const float sc = ((pr[0] - cc[0]) * e0 + (pr[1] - cc[1]) * e1 + (pr[2] - cc[2]) * e2) / (e0 * e0 + e1 * e1 + e2 * e2);
+    if (sc > bs) {
+      bs = sc;
+      best = k;
+      boff = off;
+    }
+    off += (int)f.w;
+  }
+  auto fan = [&](int k, int voff) -> bool {
+    const float4 f = R[2 + k];
+    const float fc[3] = {f.x, f.y, f.z};
+    const int len = (int)f.w;
+    const float4 *V = R + 2 + nf + voff;
+    float vp[3] = {V[0].x, V[0].y, V[0].z};
+    const float s_first = orient3f(cc, fc, vp, pr);
+    float s_prev = s_first;
+    for (int j = 0; j < len; ++j) {
+      const float4 n4 = V[j + 1 == len ? 0 : j + 1];
+      const float vn[3] = {n4.x, n4.y, n4.z};
+      const float s_next = (j + 1 == len) ? s_first : orient3f(cc, fc, vn, pr);
+      const float tol = 1e-4f * fabsf(orient3f(cc, fc, vp, vn));
+      if (s_prev > tol && -s_next > tol && orient3f(pr, fc, vp, vn) > tol && orient3f(cc, pr, vp, vn) > tol)
+        return true;
+      s_prev = s_next;
+      vp[0] = vn[0];
+      vp[1] = vn[1];
+      vp[2] = vn[2];
+    }
+    return false;
+  };
+  if (fan(best, boff)) return true;
+  off = 0;
+  for (int k = 0; k < nf; ++k) {
+    const int len = (int)R[2 + k].w;
+    if (k != best && fan(k, off)) return true;
+    off += len;
+  }
+  return false;
+}
+
+// Locate each molecule: cell_of[i] = sorted index of the cell that contains x_i, in two kernels so that
+// the rare slow cases do not hold up whole waves.
+// k_locate_fast visits molecules in the order trav (the previous binning's sorted order, so that
+// neighbouring threads read neighbouring cell records): a molecule that the FP32 records show strictly
+// inside its previous cell (hint) is in no other cell; every other molecule goes to a list.
+// k_locate_slow takes that list: the FP64 previous-cell test, then every cell whose padded box holds the
+// point, in ascending mesh cell id (the lowest containing cell wins a tie on a shared face, edge or
+// vertex).  Without FP32 records (a cell too large for the fixed stride) or without a previous binning
+// every molecule takes the slow path.
 template <typename PT>
-__global__ void k_locate(const PT *__restrict__ pos, int64_t n, const int32_t *__restrict__ trav,
-                         const int64_t *__restrict__ rec_off, const double *__restrict__ rec,
-                         const double *__restrict__ bb, const int64_t *__restrict__ gb_off,
-                         const int32_t *__restrict__ gb_cell, double glo0, double glo1, double glo2, double gh,
-                         int64_t nb0, int64_t nb1, int64_t nb2, int32_t *__restrict__ cell_of,
-                         int32_t *__restrict__ count, unsigned long long *__restrict__ status,
-                         int32_t *__restrict__ hint) {
+__global__ void k_locate_fast(const PT *__restrict__ pos, int64_t n, const int32_t *__restrict__ trav,
+                              const float4 *__restrict__ rec32, int32_t *__restrict__ cell_of,
+                              int32_t *__restrict__ count, const int32_t *__restrict__ hint,
+                              unsigned long long *__restrict__ nslow, int32_t *__restrict__ slow) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int64_t i = trav ? trav[t] : t;
+  const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
+  const int32_t h0 = hint[i];
+  if (rec32 && h0 >= 0 && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) &&
+      surely_in_rec32(p, rec32 + (int64_t)kR32 * h0)) {
+    cell_of[i] = h0;
+    atomicAdd(&count[h0], 1);
+  } else {
+    slow[atomicAdd(nslow, 1ull)] = (int32_t)i;
+  }
+}
+
+template <typename PT>
+__global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long long *__restrict__ nslow,
+                              const int32_t *__restrict__ slow, const int64_t *__restrict__ rec_off,
+                              const double *__restrict__ rec, const double *__restrict__ bb,
+                              const int64_t *__restrict__ gb_off, const int32_t *__restrict__ gb_cell, double glo0,
+                              double glo1, double glo2, double gh, int64_t nb0, int64_t nb1, int64_t nb2,
+                              int32_t *__restrict__ cell_of, int32_t *__restrict__ count,
+                              unsigned long long *__restrict__ status, int32_t *__restrict__ hint) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)*nslow) return;
+  const int64_t i = slow[t];
   const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
   const bool finite = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
   int32_t found = -1;
@@ -637,6 +729,39 @@ static int upload_geometry(aica_dil *h) {
     });
     if ((rc = upload(h->d_rec_off, roff))) return rc;
     if ((rc = upload(h->d_rec, rec))) return rc;
+    // FP32 records (layout at surely_in_rec32), when every cell fits the fixed stride
+    bool fits = true;
+    for (int64_t s = 0; s < g.nc && fits; ++s) {
+      const double *R = rec.data() + roff[s];
+      const int64_t nf = (int64_t)R[0];
+      int64_t nv = 0;
+      for (int64_t k = 0; k < nf; ++k) nv += (int64_t)R[4 + 3 * nf + k];
+      fits = 2 + nf + nv <= kR32;
+    }
+    h->has_rec32 = fits;
+    if (fits) {
+      std::vector<float4> r32((size_t)g.nc * kR32);
+      parallel_for(g.nc, [&](int64_t s0, int64_t s1, int) {
+        for (int64_t s = s0; s < s1; ++s) {
+          const double *R = rec.data() + roff[s];
+          const int64_t nf = (int64_t)R[0];
+          float4 *O = r32.data() + (size_t)s * kR32;
+          const double a[3] = {(double)(float)R[1], (double)(float)R[2], (double)(float)R[3]};
+          O[0] = make_float4((float)nf, (float)a[0], (float)a[1], (float)a[2]);
+          O[1] = make_float4((float)(R[1] - a[0]), (float)(R[2] - a[1]), (float)(R[3] - a[2]), 0.f);
+          const double *FC = R + 4, *LEN = FC + 3 * nf, *V = LEN + nf;
+          int64_t nv = 0;
+          for (int64_t k = 0; k < nf; ++k) {
+            O[2 + k] = make_float4((float)(FC[3 * k] - a[0]), (float)(FC[3 * k + 1] - a[1]), (float)(FC[3 * k + 2] - a[2]),
+                                   (float)LEN[k]);
+            nv += (int64_t)LEN[k];
+          }
+          for (int64_t j = 0; j < nv; ++j)
+            O[2 + nf + j] = make_float4((float)(V[3 * j] - a[0]), (float)(V[3 * j + 1] - a[1]), (float)(V[3 * j + 2] - a[2]), 0.f);
+        }
+      });
+      if ((rc = upload(h->d_rec32, r32))) return rc;
+    }
   }
   // padded bounding boxes (sorted cell order) and the point-location grid (sorted cell indices listed in
   // every bin their box touches, in ascending mesh cell id so the lowest containing cell is found first)
@@ -816,6 +941,7 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   if ((rc = h->d_slot_base.ensure(8 * (nc + 1)))) return rc;
   if ((rc = h->d_cell_sorted.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
   if ((rc = h->d_status.ensure(64))) return rc;
+  if ((rc = h->d_slow.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
   ProfScope ps(h, "bin", st);
   unsigned long long *status = h->d_status.as<unsigned long long>();
   hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, status, (int64_t)8, 0ull);
@@ -830,16 +956,22 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   if (n > 0) {
     // visit molecules in the previous binning's sorted order when there is one for this n
     const int32_t *trav = h->perm_n == n ? h->d_perm.as<int32_t>() : nullptr;
+    const float4 *r32 = h->has_rec32 ? h->d_rec32.as<float4>() : nullptr;
+    int32_t *slow = h->d_slow.as<int32_t>();
+    unsigned long long *nslow = status + 2;
 #define AICA_LOCATE(PT)                                                                                            \
-  hipLaunchKernelGGL((k_locate<PT>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const PT *)pos_dev, n, trav,          \
+  hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const PT *)pos_dev, n, trav, r32, \
+                     h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), h->d_hint.as<int32_t>(), nslow, slow);   \
+  hipLaunchKernelGGL((k_locate_slow<PT>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const PT *)pos_dev, nslow, slow, \
                      h->d_rec_off.as<int64_t>(), h->d_rec.as<double>(), h->d_bb.as<double>(),                      \
                      h->d_gb_off.as<int64_t>(), h->d_gb_cell.as<int32_t>(), h->glo[0], h->glo[1], h->glo[2], h->gh, \
                      h->gnb[0], h->gnb[1], h->gnb[2], h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status, \
                      h->d_hint.as<int32_t>())
-    if (pos_dtype == AICA_FP64)
+    if (pos_dtype == AICA_FP64) {
       AICA_LOCATE(double);
-    else
+    } else {
       AICA_LOCATE(float);
+    }
 #undef AICA_LOCATE
     HIPCHK(hipGetLastError());
   }
