@@ -514,3 +514,73 @@ def cutoff_band_pairs(n_side=6, spacing=8.0, seed=21):
     n = len(x)
     return Workload(f"cutoff_band_{n}", mesh, qround(x), np.zeros(n, np.int32), np.array([1.0]), np.array([1.0]),
                     2.5, np.zeros(3), np.full(3, L), (0, 1, 2))
+
+
+def refined_nodes(length, centres, half_width, h_fine, h_coarse, slope=0.5):
+    """Node coordinates on [0, length]: spacing h_fine within half_width of any centre, growing by
+    `slope` per unit distance beyond it, capped at h_coarse (rescaled to end exactly at length)."""
+    centres = np.asarray(centres, dtype=np.float64)
+
+    def h(x):
+        d = np.min(np.abs(centres - x)) if len(centres) else np.inf
+        return min(h_coarse, h_fine + slope * max(0.0, d - half_width))
+
+    xs = [0.0]
+    while xs[-1] < length:
+        xs.append(xs[-1] + h(xs[-1] + 0.5 * h(xs[-1])))
+    xs = np.array(xs)
+    if xs[-1] - length > 0.5 * (xs[-1] - xs[-2]):
+        xs = xs[:-1]
+    return xs * (length / xs[-1])
+
+
+def config3(seed=3, n_cells_target=6.0e5, post_r=8.0):
+    """Nanochannel with posts: 200 x 60 x 60 box, periodic in x and z, walls at y = 0 and 60; six posts
+    of radius 8 along z at x_k = 200 (k + 1/2) / 6, y = 30.  Tensor-product hex mesh with spacing 1
+    within 12 of a post axis (x) and of y = 30 (y), graded to at most 3 elsewhere, uniform z spacing
+    sized for about n_cells_target cells after deleting the cells whose vertices (after a +-0.25 edge
+    interior jitter) all lie inside a post.  FCC at density 0.8, sites with r_post >= 8.5 and
+    0.5 <= y <= 59.5, jitter +-0.05; Maxwell velocities at T* = 1 with zero net momentum, rescaled
+    exactly (extra["v"])."""
+    Lx, Ly, Lz = (float(qround(v)) for v in (200.0, 60.0, 60.0))
+    posts = np.array([[Lx * (k + 0.5) / 6.0, Ly / 2.0] for k in range(6)])
+    xs = refined_nodes(Lx, posts[:, 0], 12.0, 1.0, 3.0)
+    ys = refined_nodes(Ly, [Ly / 2.0], 12.0, 1.0, 3.0)
+    # cells of the x-y layer outside the posts (cell centres), to size the z spacing
+    cxm, cym = np.meshgrid(0.5 * (xs[1:] + xs[:-1]), 0.5 * (ys[1:] + ys[:-1]), indexing="ij")
+    rmin = np.min(np.hypot(cxm[..., None] - posts[:, 0], cym[..., None] - posts[:, 1]), axis=-1)
+    n_layer = int((rmin >= post_r).sum())
+    nz = max(2, int(round(n_cells_target / max(n_layer, 1))))
+    zs = uniform_nodes(Lz, nz)
+    xs, ys, zs = (qround(a) for a in (xs, ys, zs))
+    mesh = hex_mesh(xs, ys, zs, periodic_axes=(0, 2))
+    mesh = jitter_interior(mesh, xs, ys, zs, 0.25, _rng(seed, 0))
+    # delete the cells whose vertices all lie inside a post (such a cell lies inside the post, which
+    # is convex, so every point outside the posts stays in a kept cell)
+    pr = np.min(np.hypot(mesh.points[:, 0:1] - posts[:, 0], mesh.points[:, 1:2] - posts[:, 1]), axis=1)
+    lens = np.diff(mesh.face_off)
+    fmax = np.maximum.reduceat(pr[mesh.face_pts], mesh.face_off[:-1]) if len(lens) else np.zeros(0)
+    cmax = np.zeros(mesh.n_cells)
+    np.maximum.at(cmax, mesh.owner, fmax)
+    nb = mesh.neighbour >= 0
+    np.maximum.at(cmax, mesh.neighbour[nb], fmax[nb])
+    mesh = delete_cells(mesh, cmax < post_r)
+    mesh = renumber_cells(mesh, _rng(seed, 5).permutation(mesh.n_cells))
+    # molecules
+    a0 = (4.0 / 0.8) ** (1.0 / 3.0)
+    nf = (int(round(Lx / a0)), int(round(Ly / a0)), int(round(Lz / a0)))
+    a = np.array([Lx / nf[0], Ly / nf[1], Lz / nf[2]])
+    x = fcc_sites(nf, a)
+    x = x + _rng(seed, 1).uniform(-0.05, 0.05, size=x.shape)
+    r = np.min(np.hypot(x[:, 0:1] - posts[:, 0], x[:, 1:2] - posts[:, 1]), axis=1)
+    x = x[(r >= post_r + 0.5) & (x[:, 1] >= 0.5) & (x[:, 1] <= Ly - 0.5)]
+    lo, hi = np.zeros(3), np.array([Lx, Ly, Lz])
+    x = qround(wrap(qround(x), lo, hi, (0, 2)))
+    for ax in (0, 2):
+        x[:, ax] = np.where(x[:, ax] >= hi[ax], x[:, ax] - (hi[ax] - lo[ax]), x[:, ax])
+    N = len(x)
+    v = _rng(seed, 3).standard_normal((N, 3))
+    v -= v.mean(axis=0)
+    v *= np.sqrt(3.0 * N * 1.0 / (v ** 2).sum())
+    return Workload(f"posts{N}_channel200x60x60", mesh, x, np.zeros(N, np.int32), np.array([1.0]), np.array([1.0]),
+                    2.5, lo, hi, (0, 2), extra={"v": v, "posts": posts, "post_r": post_r})
