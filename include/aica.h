@@ -85,6 +85,18 @@ typedef struct aica_dil aica_dil;  /* opaque handle */
  * On success *out owns device geometry and must be freed with aica_dil_free. */
 int aica_build_dil(const aica_mesh *mesh, double rcut, double guard, aica_dil **out);
 
+#define AICA_DIL_CLOSEST 0  /* closest distance between the closed cells (no pair can be missed) */
+#define AICA_DIL_VERTEX 1   /* the paper's own test: some vertex of c and some vertex of d + t closer */
+
+/* aica_build_dil with a choice of cell-pair predicate.  AICA_DIL_VERTEX is the
+ * test of Sec. 2.2 and App. A.1 (vertex-to-vertex distance below rcut + guard);
+ * on distorted meshes it can miss cell pairs whose closest points are within
+ * range while all their vertices are not (Sec. 2.2 on twisted meshes), and
+ * then molecule pairs inside the cut-off go unevaluated.  Everything else as
+ * aica_build_dil (which is predicate AICA_DIL_CLOSEST).
+ * Errors: as aica_build_dil, plus AICA_E_INVAL for an unknown predicate. */
+int aica_build_dil_ex(const aica_mesh *mesh, double rcut, double guard, int32_t predicate, aica_dil **out);
+
 /* Per-step binning (Sec. 2.2: the library keeps which cell each molecule is
  * in).  pos_dev: device [n][3] positions in the caller's order, dtype
  * AICA_FP64 (double) or AICA_FP32 (float); every position must lie in the

@@ -607,10 +607,28 @@ double oc_cell_distance(int64_t n_points, const double *points, int64_t n_faces,
  * between cell c and cell d + sum_k n_k v_k below rc + guard, n_k in {-1,0,1},
  * reported once: c < d, or c == d with n lexicographically positive.  Returns
  * the count (arrays may be NULL to count only), or <0 on error. */
+/* The paper's own cell-pair predicate (Sec. 2.2, App. A.1): some vertex of c and some vertex of d + T
+ * are closer than R.  Brute force over all vertex pairs. */
+static int oc_vertices_in_range(const oc_cell *c, const oc_cell *d, const double *T, double R) {
+  for (int i = 0; i < c->nv; ++i)
+    for (int j = 0; j < d->nv; ++j) {
+      double s = 0;
+      for (int q = 0; q < 3; ++q) {
+        double e = c->v[3 * i + q] - (d->v[3 * j + q] + T[q]);
+        s += e * e;
+      }
+      if (s < R * R) return 1;
+    }
+  return 0;
+}
+
+/* Interacting cell pairs, canonical (c < d, or c == d with the lattice image lexicographically
+ * positive).  predicate 0: closest distance between the closed cells below rc + guard; 1: the paper's
+ * vertex-to-vertex distance below rc + guard. */
 int64_t oc_dil(int64_t n_points, const double *points, int64_t n_faces, const int64_t *face_off,
                const int32_t *face_pts, const int32_t *owner, const int32_t *neighbour, int64_t n_cells,
-               int32_t nper, const double *lat, double rc, double guard, int64_t cap, int32_t *oc, int32_t *od,
-               int8_t *on) {
+               int32_t nper, const double *lat, double rc, double guard, int32_t predicate, int64_t cap, int32_t *oc,
+               int32_t *od, int8_t *on) {
   oc_mesh m;
   oc_mesh_from(n_points, points, n_faces, face_off, face_pts, owner, neighbour, n_cells, &m);
   oc_cell *cells;
@@ -642,7 +660,8 @@ int64_t oc_dil(int64_t n_points, const double *points, int64_t n_faces, const in
         double T[3] = {0, 0, 0};
         for (int k = 0; k < nper; ++k)
           for (int q = 0; q < 3; ++q) T[q] += n[k] * lat[3 * k + q];
-        if (oc_cells_in_range(&cells[c], &cells[d], T, R)) {
+        if (predicate == 1 ? oc_vertices_in_range(&cells[c], &cells[d], T, R)
+                           : oc_cells_in_range(&cells[c], &cells[d], T, R)) {
           if (oc && cnt < cap) {
             oc[cnt] = (int32_t)c;
             od[cnt] = (int32_t)d;

@@ -44,7 +44,7 @@ def lib():
         L.oc_adjoint.argtypes = [i64, p, p, i32, p, p, f64, i32, p, p, f64, p, p, p, p]
         L.oc_adjoint.restype = C.c_int
         mesh_args = [i64, p, i64, p, p, p, p, i64]
-        L.oc_dil.argtypes = mesh_args + [i32, p, f64, f64, i64, p, p, p]
+        L.oc_dil.argtypes = mesh_args + [i32, p, f64, f64, i32, i64, p, p, p]
         L.oc_dil.restype = i64
         L.oc_locate.argtypes = mesh_args + [i64, p, p]
         L.oc_locate.restype = C.c_int
@@ -168,16 +168,18 @@ def _mesh_args(mesh):
     return keep, [len(pts), _ptr(pts), len(ow), _ptr(fo), _ptr(fp), _ptr(ow), _ptr(ne), int(mesh.n_cells)]
 
 
-def dil(mesh, rcut, guard):
-    """Brute-force interacting cell pairs as sorted rows (c, d, n0, n1, n2)."""
+def dil(mesh, rcut, guard, predicate="closest"):
+    """Brute-force interacting cell pairs as sorted rows (c, d, n0, n1, n2).  predicate "closest": the
+    closest distance between the closed cells is below rcut + guard; "vertex": some vertex pair is."""
     keep, args = _mesh_args(mesh)
     lat, nper = _lat(mesh.periodic)
-    cnt = lib().oc_dil(*args, nper, _ptr(lat), float(rcut), float(guard), 0, None, None, None)
+    pr = {"closest": 0, "vertex": 1}[predicate]
+    cnt = lib().oc_dil(*args, nper, _ptr(lat), float(rcut), float(guard), pr, 0, None, None, None)
     if cnt < 0:
         raise ValueError(f"oc_dil failed ({cnt})")
     c, d = np.zeros(cnt, np.int32), np.zeros(cnt, np.int32)
     nn = np.zeros((cnt, 3), np.int8)
-    lib().oc_dil(*args, nper, _ptr(lat), float(rcut), float(guard), cnt, _ptr(c), _ptr(d), _ptr(nn))
+    lib().oc_dil(*args, nper, _ptr(lat), float(rcut), float(guard), pr, cnt, _ptr(c), _ptr(d), _ptr(nn))
     key = np.stack([c, d, nn[:, 0], nn[:, 1], nn[:, 2]], axis=1).astype(np.int64)
     return key[np.lexsort(key.T[::-1])]
 

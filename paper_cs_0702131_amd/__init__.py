@@ -27,7 +27,9 @@ def _c(a, dt):
 class DIL:
     """Owns an aica_dil handle: the mesh's interaction lists and the per-step binning state."""
 
-    def __init__(self, mesh, rcut, guard=None):
+    def __init__(self, mesh, rcut, guard=None, predicate="closest"):
+        """predicate "closest" (default): cell pairs whose closest points are within rcut + guard;
+        "vertex": the paper's vertex-to-vertex test, which can miss pairs on distorted meshes."""
         self.rcut = float(rcut)
         self.guard = 1e-6 * self.rcut if guard is None else float(guard)
         pts = _c(mesh.points, np.float64)
@@ -45,7 +47,8 @@ class DIL:
             for q in range(3):
                 m.periodic_vec[k][q] = per[k, q]
         h = C.c_void_p()
-        check(lib().aica_build_dil(C.byref(m), self.rcut, self.guard, C.byref(h)))
+        pred = {"closest": _lib.AICA_DIL_CLOSEST, "vertex": _lib.AICA_DIL_VERTEX}[predicate]
+        check(lib().aica_build_dil_ex(C.byref(m), self.rcut, self.guard, pred, C.byref(h)))
         self.h = h
         self.n_cells = int(mesh.n_cells)
         self._pos = None
@@ -81,8 +84,8 @@ class DIL:
         return ms.value, n.value
 
 
-def aica_build_dil(mesh, rcut, guard=None):
-    return DIL(mesh, rcut, guard)
+def aica_build_dil(mesh, rcut, guard=None, predicate="closest"):
+    return DIL(mesh, rcut, guard, predicate)
 
 
 def _stream(t):

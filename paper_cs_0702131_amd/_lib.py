@@ -22,7 +22,10 @@ AICA_FP64 = 2
 ERROR_NAMES = {AICA_E_INVAL: "AICA_E_INVAL", AICA_E_MESH: "AICA_E_MESH", AICA_E_RCUT: "AICA_E_RCUT",
                AICA_E_UNLOCATED: "AICA_E_UNLOCATED", AICA_E_NOMEM: "AICA_E_NOMEM", AICA_E_HIP: "AICA_E_HIP"}
 
-EXPORTED = ["aica_build_dil", "aica_bin", "aica_forces", "aica_forces_adjoint", "aica_dil_export",
+AICA_DIL_CLOSEST = 0
+AICA_DIL_VERTEX = 1
+
+EXPORTED = ["aica_build_dil", "aica_build_dil_ex", "aica_bin", "aica_forces", "aica_forces_adjoint", "aica_dil_export",
             "aica_pairs_export", "aica_bin_export", "aica_dil_info", "aica_work_stats", "aica_profile", "aica_profile_read",
             "aica_last_error", "aica_dil_free"]
 
@@ -65,6 +68,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         p, i64, i32, f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double
         L.aica_build_dil.argtypes = [C.POINTER(aica_mesh), f64, f64, C.POINTER(p)]
+        L.aica_build_dil_ex.argtypes = [C.POINTER(aica_mesh), f64, f64, i32, C.POINTER(p)]
         L.aica_bin.argtypes = [p, p, i32, i64, p]
         L.aica_forces.argtypes = [p, p, p, C.POINTER(aica_params), p, p, p, p]
         L.aica_forces_adjoint.argtypes = [p, p, p, C.POINTER(aica_params), p, f64, p, p, p, p]

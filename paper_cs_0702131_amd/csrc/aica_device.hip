@@ -869,8 +869,14 @@ static int ensure_groups(aica_dil *h, int64_t n) {
 const char *aica_last_error(void) { return last_error_cstr(); }
 
 int aica_build_dil(const aica_mesh *mesh, double rcut, double guard, aica_dil **out) {
+  return aica_build_dil_ex(mesh, rcut, guard, AICA_DIL_CLOSEST, out);
+}
+
+int aica_build_dil_ex(const aica_mesh *mesh, double rcut, double guard, int32_t predicate, aica_dil **out) {
   if (!out) return fail(AICA_E_INVAL, "out is NULL");
   *out = nullptr;
+  if (predicate != AICA_DIL_CLOSEST && predicate != AICA_DIL_VERTEX)
+    return fail(AICA_E_INVAL, "predicate must be AICA_DIL_CLOSEST or AICA_DIL_VERTEX");
   if (!(rcut > 0) || !std::isfinite(rcut) || !(guard >= 0) || !std::isfinite(guard))
     return fail(AICA_E_INVAL, "rcut must be > 0 and guard >= 0");
   auto t0 = std::chrono::steady_clock::now();
@@ -887,7 +893,7 @@ int aica_build_dil(const aica_mesh *mesh, double rcut, double guard, aica_dil **
   auto t1 = std::chrono::steady_clock::now();
   spatial_order(h->geo, h->order, h->rank);
   auto t2 = std::chrono::steady_clock::now();
-  rc = build_cell_pairs(h->geo, h->order, h->rank, rcut + guard, h->pairs);
+  rc = build_cell_pairs(h->geo, h->order, h->rank, rcut + guard, predicate, h->pairs);
   if (verbose)
     fprintf(stderr, "aica_build_dil: geometry %.2fs order %.2fs pairs %.2fs (%zu)\n",
             std::chrono::duration<double>(t1 - t0).count(), std::chrono::duration<double>(t2 - t1).count(),

@@ -83,7 +83,7 @@ struct CellPair {
 // Build the direct interaction lists (App. A.1 with the closest-point predicate and
 // guard of Sec. 2.2) including periodic referred pairs (lattice translations).
 int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const std::vector<int32_t> &rank,
-                     double R, std::vector<CellPair> &out);
+                     double R, int predicate, std::vector<CellPair> &out);
 
 // Interaction groups: consecutive sorted cells packed to an expected occupancy target.
 struct Groups {

@@ -450,8 +450,22 @@ static bool cells_in_range(const Geometry &g, int32_t c, int32_t d, const V3 &T,
 
 static inline int img_code(int n0, int n1, int n2) { return 9 * (n0 + 1) + 3 * (n1 + 1) + (n2 + 1); }
 
+// Closest-distance predicate (predicate AICA_DIL_CLOSEST), or the paper's vertex-to-vertex predicate
+// (AICA_DIL_VERTEX: some vertex of c and some vertex of d + T closer than R).
+static bool vertices_in_range(const Geometry &g, int32_t c, int32_t d, const V3 &T, double R) {
+  const double R2 = R * R;
+  for (int64_t i = g.cv_off[c]; i < g.cv_off[c + 1]; ++i) {
+    const V3 a = mk(&g.pts[3 * (int64_t)g.cv[i]]);
+    for (int64_t j = g.cv_off[d]; j < g.cv_off[d + 1]; ++j) {
+      const V3 b = mk(&g.pts[3 * (int64_t)g.cv[j]]) + T;
+      if (dot(a - b, a - b) < R2) return true;
+    }
+  }
+  return false;
+}
+
 int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const std::vector<int32_t> &rank,
-                     double R, std::vector<CellPair> &out) {
+                     double R, int predicate, std::vector<CellPair> &out) {
   for (int k = 0; k < g.nper; ++k) {
     double L = std::sqrt(dot(mk(g.per[k]), mk(g.per[k])));
     if (!(R < 0.5 * L))
@@ -556,7 +570,13 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
                     if (sd < sc || (sd == sc && code <= 13)) continue;  // canonical half
                     int q = quick_range(box[sc], box[sd], T, R);
                     ++stat_cand;
-                    if (q < 0) {
+                    if (predicate == AICA_DIL_VERTEX) {
+                      // the bounding boxes hold the vertices: only their gap may decide
+                      if (q != 0) {
+                        ++stat_exact;
+                        q = vertices_in_range(g, c, order[sd], T, R) ? 1 : 0;
+                      }
+                    } else if (q < 0) {
                       ++stat_exact;
                       q = cells_in_range(g, c, order[sd], T, R, tc, td) ? 1 : 0;
                     }

@@ -30,12 +30,18 @@ def test_library_exports_every_declared_symbol(A):
 
 
 def _dil_case(mesh, rcut, guard, A, oracle):
-    d = A.DIL(mesh, rcut, guard)
-    got = A.aica_dil_export(d)
-    ref = oracle.dil(mesh, rcut, guard)
-    assert np.array_equal(got, ref), (len(got), len(ref))
-    d.close()
-    return got
+    """Both cell-pair predicates bit-exact against the brute force; the vertex list is a subset."""
+    out = {}
+    for pred in ("closest", "vertex"):
+        d = A.DIL(mesh, rcut, guard, predicate=pred)
+        got = A.aica_dil_export(d)
+        ref = oracle.dil(mesh, rcut, guard, pred)
+        assert np.array_equal(got, ref), (pred, len(got), len(ref))
+        d.close()
+        out[pred] = got
+    closest = {tuple(r) for r in out["closest"]}
+    assert all(tuple(r) in closest for r in out["vertex"])
+    return out["closest"]
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -71,10 +77,34 @@ def test_dil_matches_bruteforce_deleted_cells(A, oracle):
 
 @pytest.mark.parametrize("ratio,nc", [(1.0, 27), (1.25, 81), (1.914, 125), (2.5, 275)])
 def test_dil_counts_uniform_cubes(A, ratio, nc):
+    # on axis-aligned unit cubes the closest points of two cells are vertices, so both predicates
+    # give the same N_c
     nodes = np.arange(7.0)
     m = W.hex_mesh(nodes, nodes, nodes, periodic_axes=(0, 1, 2), shuffle_seed=5)
-    d = A.DIL(m, ratio, 0.0)
-    assert d.info()["n_dil"] == m.n_cells * (nc - 1) // 2
+    for pred in ("closest", "vertex"):
+        d = A.DIL(m, ratio, 0.0, predicate=pred)
+        assert d.info()["n_dil"] == m.n_cells * (nc - 1) // 2
+
+
+def test_vertex_predicate_misses_on_distorted_mesh(A, oracle):
+    # strongly jittered hexes: some cell pairs are within range only between face or edge interiors;
+    # the vertex predicate drops exactly those (their vertex pairs are all out of range)
+    wl = W.small_random(n_mesh=(5, 5, 5), L=(9.0, 9.0, 9.0), N=10, seed=4, mesh_jitter=0.3)
+    m = wl.mesh
+    dc = {tuple(r) for r in A.aica_dil_export(A.DIL(m, 2.5, 0.0, predicate="closest"))}
+    dv = {tuple(r) for r in A.aica_dil_export(A.DIL(m, 2.5, 0.0, predicate="vertex"))}
+    missed = dc - dv
+    assert dv <= dc and len(missed) > 0
+    cv = {}
+    for c in range(m.n_cells):
+        f = np.nonzero((m.owner == c) | (m.neighbour == c))[0]
+        cv[c] = np.unique(np.concatenate([m.face_pts[m.face_off[k]:m.face_off[k + 1]] for k in f]))
+    lat = np.asarray(m.periodic).reshape(-1, 3)
+    for c, d, n0, n1, n2 in sorted(missed)[:50]:
+        T = np.array([n0, n1, n2])[:len(lat)] @ lat if len(lat) else np.zeros(3)
+        vd = np.sqrt(((m.points[cv[c]][:, None, :] - m.points[cv[d]][None, :, :] - T) ** 2).sum(-1)).min()
+        assert vd >= 2.5
+        assert oracle.cell_distance(m, c, d, T) < 2.5
 
 
 def test_dil_k5(A):

@@ -228,6 +228,8 @@ def test_dil_counts_on_uniform_cubes(oracle, ratio, nc):
     m = W.hex_mesh(nodes, nodes, nodes, periodic_axes=(0, 1, 2), shuffle_seed=2)
     D = oracle.dil(m, ratio, 0.0)
     assert len(D) == m.n_cells * (nc - 1) // 2
+    # the paper's vertex-to-vertex predicate gives the same lists on axis-aligned cubes (Sec. 2.4)
+    assert np.array_equal(oracle.dil(m, ratio, 0.0, "vertex"), D)
     # no cell on its own list with a zero image; (c,c,n) only with n > 0
     same = D[D[:, 0] == D[:, 1]]
     assert not np.any((same[:, 2:] == 0).all(axis=1))
