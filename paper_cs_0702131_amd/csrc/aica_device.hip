@@ -90,6 +90,7 @@ struct aica_dil {
   // device geometry for point location (mesh cell ids)
   DBuf d_rec_off, d_rec, d_bb;  // point-location cell records and padded boxes, sorted cell order
   DBuf d_rec32;                 // FP32 records for the previous-cell test (cells of at most kR32 float4)
+  DBuf d_nbr_off, d_nbr;        // cells across each cell's interior faces (sorted ids)
   bool has_rec32 = false;
   DBuf d_gb_off, d_gb_cell;
   double glo[3] = {0, 0, 0}, gh = 1;
@@ -260,9 +261,10 @@ __device__ bool surely_in_rec32(const double *p, const float4 *R) {
 // k_locate_fast visits molecules in the order trav (the previous binning's sorted order, so that
 // neighbouring threads read neighbouring cell records): a molecule that the FP32 records show strictly
 // inside its previous cell (hint) is in no other cell; every other molecule goes to a list.
-// k_locate_slow takes that list: the FP64 previous-cell test, then every cell whose padded box holds the
-// point, in ascending mesh cell id (the lowest containing cell wins a tie on a shared face, edge or
-// vertex).  Without FP32 records (a cell too large for the fixed stride) or without a previous binning
+// k_locate_slow takes that list: the FP64 previous-cell test; then the cells across the previous cell's
+// faces (a molecule that left its cell has crossed one of them: the paper's membership tracking), each
+// accepted only when the point is strictly inside; then every cell whose padded box holds the point, in
+// ascending mesh cell id (the lowest containing cell wins a tie on a shared face, edge or vertex).  Without FP32 records (a cell too large for the fixed stride) or without a previous binning
 // every molecule takes the slow path.
 template <typename PT>
 __global__ void k_locate_fast(const PT *__restrict__ pos, int64_t n, const int32_t *__restrict__ trav,
@@ -286,7 +288,8 @@ __global__ void k_locate_fast(const PT *__restrict__ pos, int64_t n, const int32
 template <typename PT>
 __global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long long *__restrict__ nslow,
                               const int32_t *__restrict__ slow, const int64_t *__restrict__ rec_off,
-                              const double *__restrict__ rec, const double *__restrict__ bb,
+                              const double *__restrict__ rec, const int64_t *__restrict__ nbr_off,
+                              const int32_t *__restrict__ nbr, const double *__restrict__ bb,
                               const int64_t *__restrict__ gb_off, const int32_t *__restrict__ gb_cell, double glo0,
                               double glo1, double glo2, double gh, int64_t nb0, int64_t nb1, int64_t nb2,
                               int32_t *__restrict__ cell_of, int32_t *__restrict__ count,
@@ -298,7 +301,17 @@ __global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long lo
   const bool finite = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
   int32_t found = -1;
   const int32_t h0 = hint[i];
-  if (h0 >= 0 && finite && point_in_rec(p, rec + rec_off[h0], -1e-9)) found = h0;
+  if (h0 >= 0 && finite) {
+    if (point_in_rec(p, rec + rec_off[h0], -1e-9)) {
+      found = h0;
+    } else {
+      for (int64_t k = nbr_off[h0]; k < nbr_off[h0 + 1]; ++k)
+        if (point_in_rec(p, rec + rec_off[nbr[k]], -1e-9)) {
+          found = nbr[k];
+          break;
+        }
+    }
+  }
   if (found < 0 && finite) {
     const double f0 = floor((p[0] - glo0) / gh), f1 = floor((p[1] - glo1) / gh), f2 = floor((p[2] - glo2) / gh);
     if (f0 >= 0 && f1 >= 0 && f2 >= 0 && f0 < (double)nb0 && f1 < (double)nb1 && f2 < (double)nb2) {
@@ -763,6 +776,27 @@ static int upload_geometry(aica_dil *h) {
       if ((rc = upload(h->d_rec32, r32))) return rc;
     }
   }
+  // cells across each cell's interior faces, sorted ids in sorted cell order
+  {
+    std::vector<int64_t> noff(g.nc + 1, 0);
+    const int64_t nf = g.nf;
+    for (int64_t f = 0; f < nf; ++f)
+      if (g.nei[f] >= 0) {
+        noff[h->rank[g.own[f]] + 1]++;
+        noff[h->rank[g.nei[f]] + 1]++;
+      }
+    for (int64_t s = 0; s < g.nc; ++s) noff[s + 1] += noff[s];
+    std::vector<int32_t> nb(noff[g.nc]);
+    std::vector<int64_t> fill(noff.begin(), noff.end() - 1);
+    for (int64_t f = 0; f < nf; ++f)
+      if (g.nei[f] >= 0) {
+        const int32_t a = h->rank[g.own[f]], b = h->rank[g.nei[f]];
+        nb[fill[a]++] = b;
+        nb[fill[b]++] = a;
+      }
+    if ((rc = upload(h->d_nbr_off, noff))) return rc;
+    if ((rc = upload(h->d_nbr, nb))) return rc;
+  }
   // padded bounding boxes (sorted cell order) and the point-location grid (sorted cell indices listed in
   // every bin their box touches, in ascending mesh cell id so the lowest containing cell is found first)
   std::vector<double> bb(6 * g.nc);
@@ -969,10 +1003,10 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const PT *)pos_dev, n, trav, r32, \
                      h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), h->d_hint.as<int32_t>(), nslow, slow);   \
   hipLaunchKernelGGL((k_locate_slow<PT>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const PT *)pos_dev, nslow, slow, \
-                     h->d_rec_off.as<int64_t>(), h->d_rec.as<double>(), h->d_bb.as<double>(),                      \
-                     h->d_gb_off.as<int64_t>(), h->d_gb_cell.as<int32_t>(), h->glo[0], h->glo[1], h->glo[2], h->gh, \
-                     h->gnb[0], h->gnb[1], h->gnb[2], h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status, \
-                     h->d_hint.as<int32_t>())
+                     h->d_rec_off.as<int64_t>(), h->d_rec.as<double>(), h->d_nbr_off.as<int64_t>(),               \
+                     h->d_nbr.as<int32_t>(), h->d_bb.as<double>(), h->d_gb_off.as<int64_t>(),                       \
+                     h->d_gb_cell.as<int32_t>(), h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1],      \
+                     h->gnb[2], h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status, h->d_hint.as<int32_t>())
     if (pos_dtype == AICA_FP64) {
       AICA_LOCATE(double);
     } else {
