@@ -103,10 +103,14 @@ int aica_build_dil_ex(const aica_mesh *mesh, double rcut, double guard, int32_t 
  * mesh (periodic coordinates already wrapped by the caller).  Locates each
  * molecule's cell (lowest cell index on a shared face), builds the CSR cell
  * occupancy and the cell-sorted order (ascending molecule id within a cell),
- * and the per-step work list.  Results stay in the handle.  Synchronises the
- * stream once to read the unlocated count.
- * Errors: AICA_E_INVAL (n < 0, null, bad dtype), AICA_E_UNLOCATED (the
- * count is in aica_last_error), AICA_E_NOMEM, AICA_E_HIP. */
+ * and the per-step work list.  Results stay in the handle.  Membership is
+ * tracked from the previous call with the same n (Sec. 2.2): the previous
+ * cell is tested first, then the cells across its faces, then a background
+ * grid; the answer does not depend on the history.  Synchronises the stream
+ * twice to read the unlocated and over-occupied counts.
+ * Errors: AICA_E_INVAL (n < 0 or n >= 2^28 - 1, null, bad dtype, or a cell
+ * holding more than 192 molecules), AICA_E_UNLOCATED (the count is in
+ * aica_last_error), AICA_E_NOMEM (more than 2^31 reaction records), AICA_E_HIP. */
 int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, void *hip_stream);
 
 /* Per-step forces (Sec. 2.3.1 real-real and 2.3.2 real-referred loops, with
@@ -121,7 +125,9 @@ int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, v
  * dtype (float for AICA_FP32, double for AICA_FP64), caller order, overwritten.
  * uw_dev: device double[2] = {U, W}, overwritten; npairs_dev: device int64,
  * overwritten.  Either may be NULL.  Results are deterministic (fixed
- * summation order, no atomics on forces).  Errors: AICA_E_INVAL, AICA_E_NOMEM,
+ * summation order, no atomics on forces).  With AICA_FP32 the cut-off is still
+ * decided exactly for positions that are multiples of 2^-15 (pairs within
+ * 2^-20 rc^2 of rc^2 are decided in FP64).  Errors: AICA_E_INVAL, AICA_E_NOMEM,
  * AICA_E_HIP. */
 int aica_forces(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
                 void *forces_dev, double *uw_dev, int64_t *npairs_dev, void *hip_stream);
@@ -133,8 +139,9 @@ int aica_forces(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, 
  * grad_forces_dev: device [n][3] in the compute dtype (G), caller order.
  * grad_energy: gamma (host scalar).  grad_pos_dev: device [n][3] compute dtype,
  * overwritten.  grad_eps_dev, grad_sigma_dev: device double[n_species],
- * overwritten (either may be NULL).  Same preconditions as aica_forces.
- * Errors: AICA_E_INVAL, AICA_E_NOMEM, AICA_E_HIP. */
+ * overwritten (either may be NULL).  Same preconditions as aica_forces;
+ * params->n_species must be 1 or 2.
+ * Errors: AICA_E_INVAL (also for more than two species), AICA_E_NOMEM, AICA_E_HIP. */
 int aica_forces_adjoint(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
                         const void *grad_forces_dev, double grad_energy, void *grad_pos_dev, double *grad_eps_dev,
                         double *grad_sigma_dev, void *hip_stream);
@@ -161,15 +168,15 @@ int aica_bin_export(const aica_dil *dil, int32_t *cell_of, int32_t *order, int64
 typedef struct aica_info {
   int64_t n_cells, n_dil, n_groups, n_group_pairs, n_molecules, n_jslots;
   double mesh_volume, build_seconds, group_seconds;
-  int64_t lane_steps;       /* lane-pair evaluations of the last aica_forces (tile work) */
+  int64_t lane_steps;       /* reserved (-1) */
 } aica_info;
 int aica_dil_info(const aica_dil *dil, aica_info *info);
 
 /* Work of the last aica_bin's occupancy, counted on the host:
  *   dil_candidates: molecule pairs the interaction lists make candidates (the method's own
  *                   candidate set: sum over listed cell pairs of n_c n_d, plus n_c (n_c - 1) / 2 per cell);
- *   lane_pairs:     pair evaluations the GPU tile schedule executes (16 x 16 per tile, 16 x 8 per
- *                   half tile), padding included. */
+ *   lane_pairs:     pair evaluations the GPU tiles executed in the last aica_forces on this
+ *                   binning (64 per wave-step, padding included; AICA_E_INVAL before one). */
 int aica_work_stats(const aica_dil *dil, int64_t *dil_candidates, int64_t *lane_pairs);
 
 /* Kernel timing with HIP events on the caller's stream: enable, then read the
