@@ -109,7 +109,7 @@ int aica_build_dil_ex(const aica_mesh *mesh, double rcut, double guard, int32_t 
  * grid; the answer does not depend on the history.  Synchronises the stream
  * twice to read the unlocated and over-occupied counts.
  * Errors: AICA_E_INVAL (n < 0 or n >= 2^28 - 1, null, bad dtype, or a cell
- * holding more than 256 molecules), AICA_E_UNLOCATED (the count is in
+ * holding more than 192 molecules), AICA_E_UNLOCATED (the count is in
  * aica_last_error), AICA_E_NOMEM (more than 2^31 reaction records), AICA_E_HIP. */
 int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, void *hip_stream);
 
