@@ -62,6 +62,10 @@ struct DBuf {
   T *as() const {
     return (T *)p;
   }
+  void swap(DBuf &o) {
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+  }
 };
 
 template <class T>
@@ -108,9 +112,9 @@ struct aica_dil {
   int32_t bin_dtype = 0;
   int64_t jtotal = 0;
   DBuf d_cell_of, d_count, d_cell_start, d_fill, d_perm, d_g_start, d_mol_group, d_jcnt, d_slot_base, d_cell_sorted;
-  DBuf d_scan_tmp, d_status, d_hint, d_slow;
-  int64_t hint_n = -1;  // molecule count the hints belong to (-1: none)
-  int64_t perm_n = -1;  // molecule count of the permutation held in d_perm (-1: none)
+  DBuf d_scan_tmp, d_status, d_slow;
+  DBuf d_perm_prev;     // the previous binning's permutation during aica_bin
+  int64_t perm_n = -1;  // molecule count of the binning held in d_perm and d_cell_sorted (-1: none)
   // force / adjoint workspace
   DBuf d_pos, d_own, d_jpart, d_gpart, d_gnp, d_gG, d_gpar;
   DBuf d_pairs, d_pcount;
@@ -266,41 +270,46 @@ __device__ bool surely_in_rec32(const double *p, const float4 *R) {
 // accepted only when the point is strictly inside; then every cell whose padded box holds the point, in
 // ascending mesh cell id (the lowest containing cell wins a tie on a shared face, edge or vertex).  Without FP32 records (a cell too large for the fixed stride) or without a previous binning
 // every molecule takes the slow path.
+// Both kernels index their state by t, the molecule's slot in the previous binning's sorted order
+// (trav[t] = its caller index, hint[t] = its previous cell; without a previous binning t is the
+// caller index and there is no hint), so that only the positions are read out of order.
 template <typename PT>
 __global__ void k_locate_fast(const PT *__restrict__ pos, int64_t n, const int32_t *__restrict__ trav,
-                              const float4 *__restrict__ rec32, int32_t *__restrict__ cell_of,
-                              int32_t *__restrict__ count, const int32_t *__restrict__ hint,
+                              const int32_t *__restrict__ hint, const float4 *__restrict__ rec32,
+                              int32_t *__restrict__ cell_t, int32_t *__restrict__ count,
                               unsigned long long *__restrict__ nslow, int32_t *__restrict__ slow) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int64_t i = trav ? trav[t] : t;
   const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
-  const int32_t h0 = hint[i];
+  const int32_t h0 = hint ? hint[t] : -1;
   if (rec32 && h0 >= 0 && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) &&
       surely_in_rec32(p, rec32 + (int64_t)kR32 * h0)) {
-    cell_of[i] = h0;
+    cell_t[t] = h0;
     atomicAdd(&count[h0], 1);
   } else {
-    slow[atomicAdd(nslow, 1ull)] = (int32_t)i;
+    slow[atomicAdd(nslow, 1ull)] = (int32_t)t;
   }
 }
 
 template <typename PT>
 __global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long long *__restrict__ nslow,
-                              const int32_t *__restrict__ slow, const int64_t *__restrict__ rec_off,
+                              const int32_t *__restrict__ slow, const int32_t *__restrict__ trav,
+                              const int32_t *__restrict__ hint, const int64_t *__restrict__ rec_off,
                               const double *__restrict__ rec, const int64_t *__restrict__ nbr_off,
                               const int32_t *__restrict__ nbr, const double *__restrict__ bb,
                               const int64_t *__restrict__ gb_off, const int32_t *__restrict__ gb_cell, double glo0,
                               double glo1, double glo2, double gh, int64_t nb0, int64_t nb1, int64_t nb2,
-                              int32_t *__restrict__ cell_of, int32_t *__restrict__ count,
-                              unsigned long long *__restrict__ status, int32_t *__restrict__ hint) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)*nslow) return;
-  const int64_t i = slow[t];
+                              int32_t *__restrict__ cell_t, int32_t *__restrict__ count,
+                              unsigned long long *__restrict__ status) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= (int64_t)*nslow) return;
+  const int64_t t = slow[u];
+  const int64_t i = trav ? trav[t] : t;
   const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
   const bool finite = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
   int32_t found = -1;
-  const int32_t h0 = hint[i];
+  const int32_t h0 = hint ? hint[t] : -1;
   if (h0 >= 0 && finite) {
     if (point_in_rec(p, rec + rec_off[h0], -1e-9)) {
       found = h0;
@@ -327,12 +336,11 @@ __global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long lo
       }
     }
   }
-  cell_of[i] = found;
+  cell_t[t] = found;
   if (found < 0)
     atomicAdd(status, 1ull);
   else
     atomicAdd(&count[found], 1);
-  hint[i] = found;
 }
 
 // ---- exclusive scan of int32 counts into OutT offsets (out[n] = total)
@@ -408,13 +416,13 @@ __global__ void k_scan_add(OutT *out, int64_t n, const OutT *tile_sum) {
   if (i < n) out[i] += tile_sum[i / kScanTile];
 }
 
-__global__ void k_scatter(const int32_t *cell_sorted, int64_t n, const int32_t *cell_start, int32_t *fill,
-                          int32_t *perm) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t c = cell_sorted[i];
+__global__ void k_scatter(const int32_t *cell_t, const int32_t *trav, int64_t n, const int32_t *cell_start,
+                          int32_t *fill, int32_t *perm) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int32_t c = cell_t[t];
   const int32_t slot = cell_start[c] + atomicAdd(&fill[c], 1);
-  perm[slot] = (int32_t)i;
+  perm[slot] = trav ? trav[t] : (int32_t)t;
 }
 
 // Ascending molecule id inside every cell (the scatter's atomics leave an arbitrary order).
@@ -987,26 +995,26 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, status, (int64_t)8, 0ull);
   hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(), nc, 0);
   hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_fill.as<int32_t>(), nc, 0);
-  if (h->hint_n != n) {
-    if ((rc = h->d_hint.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
-    hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(std::max<int64_t>(n, 1), 256)), dim3(256), 0, st,
-                       h->d_hint.as<int32_t>(), std::max<int64_t>(n, 1), -1);
-    h->hint_n = n;
-  }
+  // the previous binning of the same n (if any) gives the traversal order and the hints: its
+  // permutation moves to d_perm_prev, and d_cell_sorted still holds its cells until rebuilt below
+  const bool prev = h->perm_n == n && n > 0;
+  h->perm_n = -1;
+  if (prev) h->d_perm.swap(h->d_perm_prev);
+  if ((rc = h->d_perm.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
+  const int32_t *trav = prev ? h->d_perm_prev.as<int32_t>() : nullptr;
+  const int32_t *hint = prev ? h->d_cell_sorted.as<int32_t>() : nullptr;
   if (n > 0) {
-    // visit molecules in the previous binning's sorted order when there is one for this n
-    const int32_t *trav = h->perm_n == n ? h->d_perm.as<int32_t>() : nullptr;
     const float4 *r32 = h->has_rec32 ? h->d_rec32.as<float4>() : nullptr;
     int32_t *slow = h->d_slow.as<int32_t>();
     unsigned long long *nslow = status + 2;
 #define AICA_LOCATE(PT)                                                                                            \
-  hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const PT *)pos_dev, n, trav, r32, \
-                     h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), h->d_hint.as<int32_t>(), nslow, slow);   \
+  hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const PT *)pos_dev, n, trav, hint, \
+                     r32, h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), nslow, slow);                       \
   hipLaunchKernelGGL((k_locate_slow<PT>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const PT *)pos_dev, nslow, slow, \
-                     h->d_rec_off.as<int64_t>(), h->d_rec.as<double>(), h->d_nbr_off.as<int64_t>(),               \
+                     trav, hint, h->d_rec_off.as<int64_t>(), h->d_rec.as<double>(), h->d_nbr_off.as<int64_t>(),   \
                      h->d_nbr.as<int32_t>(), h->d_bb.as<double>(), h->d_gb_off.as<int64_t>(),                       \
                      h->d_gb_cell.as<int32_t>(), h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1],      \
-                     h->gnb[2], h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status, h->d_hint.as<int32_t>())
+                     h->gnb[2], h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status)
     if (pos_dtype == AICA_FP64) {
       AICA_LOCATE(double);
     } else {
@@ -1021,9 +1029,8 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   if (unl > 0) return fail(AICA_E_UNLOCATED, std::to_string(unl) + " molecule(s) lie in no mesh cell");
   hipLaunchKernelGGL(k_max_count, dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(), nc, status);
   if ((rc = scan_exclusive<int32_t>(h, h->d_count.as<int32_t>(), nc, h->d_cell_start.as<int32_t>(), st))) return rc;
-  h->perm_n = -1;
   if (n > 0)
-    hipLaunchKernelGGL(k_scatter, dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_cell_of.as<int32_t>(), n,
+    hipLaunchKernelGGL(k_scatter, dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_cell_of.as<int32_t>(), trav, n,
                        h->d_cell_start.as<int32_t>(), h->d_fill.as<int32_t>(), h->d_perm.as<int32_t>());
   hipLaunchKernelGGL(k_sort_cells, dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_cell_start.as<int32_t>(), nc,
                      h->d_perm.as<int32_t>());
@@ -1311,9 +1318,10 @@ int aica_bin_export(const aica_dil *h, int32_t *cell_of, int32_t *order, int64_t
   if (!h->bin_valid) return fail(AICA_E_INVAL, "aica_bin must succeed first");
   const int64_t n = h->n, nc = h->geo.nc;
   if (cell_of && n > 0) {
-    std::vector<int32_t> cs(n);
-    HIPCHK(hipMemcpy(cs.data(), h->d_cell_of.p, 4 * n, hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < n; ++i) cell_of[i] = h->order[cs[i]];
+    std::vector<int32_t> cs(n), pm(n);
+    HIPCHK(hipMemcpy(cs.data(), h->d_cell_sorted.p, 4 * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(pm.data(), h->d_perm.p, 4 * n, hipMemcpyDeviceToHost));
+    for (int64_t s = 0; s < n; ++s) cell_of[pm[s]] = h->order[cs[s]];
   }
   if (order && n > 0) HIPCHK(hipMemcpy(order, h->d_perm.p, 4 * n, hipMemcpyDeviceToHost));
   if (cell_count) {
