@@ -279,3 +279,31 @@ def test_vertex_predicate_missed_pairs(A, oracle, cfg):
     if cfg == "config2":
         Pr = oracle.pairs(wl.x, wl.rcut, wl.mesh.periodic)
         assert len(Pr) == len(keys["closest"])
+
+
+def test_binning_ties_on_faces_edges_vertices(A, oracle):
+    """Molecules exactly on shared faces, edges and vertices of an unjittered mesh with shuffled cell
+    ids: the lowest containing cell wins, on the first binning (no history), on a repeat (every
+    molecule starts from its previous cell) and after moving onto other boundaries."""
+    import torch
+    L = 8.0
+    nodes = W.uniform_nodes(L, 4)
+    mesh = W.hex_mesh(nodes, nodes, nodes, periodic_axes=(0, 1, 2), shuffle_seed=21)
+    rng = np.random.default_rng(22)
+    g = np.arange(4) * 2.0
+    pts = []
+    for _ in range(300):
+        p = rng.uniform(0.1, L - 0.1, size=3)
+        k = rng.integers(1, 4)                        # 1, 2 or 3 coordinates on grid planes
+        axes = rng.choice(3, size=k, replace=False)
+        p[axes] = g[rng.integers(0, 4, size=k)]
+        pts.append(p)
+    x = W.qround(np.array(pts))
+    d = A.DIL(mesh, 2.5)
+    for step in range(3):
+        if step == 2:
+            x = np.roll(x, 1, axis=0)                 # every molecule jumps to another boundary point
+        t = torch.tensor(x, device="cuda")
+        A.aica_bin(d, t)
+        cell_of, order, count = A.aica_bin_export(d, len(x))
+        assert np.array_equal(cell_of, oracle.locate(mesh, x)), step
