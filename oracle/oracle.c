@@ -22,9 +22,15 @@
  * axis-aligned bounding boxes farther apart than the threshold prove they are
  * not.  Row sums use a fixed order, so results are bit-reproducible.
  *
- * Images: for each periodic lattice vector v_k the oracle sums n_k in
- * [-m_k, m_k] with m_k = ceil(rc / |v_k|) (lattice vectors must be mutually
- * orthogonal).  When rc < |v_k|/2 this reduces to the minimum image.
+ * Images: every periodic direction k has a referring transform
+ * T_k(x) = R_k x + y_k (Sec. 2.2.2, generic form P' = y + R.P).  R_k = I is a
+ * lattice translation by y_k; the oracle sums n_k in [-m_k, m_k] with
+ * m_k = ceil(rc / |y_k|) (translations must be mutually orthogonal), which is
+ * the minimum image when rc < |y_k|/2.  R_k != I (a rotation) must generate a
+ * finite group (T_k^K = identity for some K <= 64); the oracle then sums all K
+ * distinct powers, so the image sum is complete without any range argument.
+ * Image n is the composition T_1^n_1 T_2^n_2 T_3^n_3 (the transforms must
+ * commute); rot == NULL means every R_k = I.
  */
 #include <math.h>
 #include <stdint.h>
@@ -55,52 +61,192 @@ void oc_lj(double s, double eps, double sig, double *u, double *g) {
 
 /* ------------------------------------------------------------------ images */
 
-static int oc_images(int nper, const double *lat, double rc, double *img /*[max][3]*/, int *code /*[max][3]*/, int maxn) {
-  int m[3] = {0, 0, 0};
+/* A referring transform x -> R x + y and the powers n of the generators it composes. */
+typedef struct {
+  double R[9];
+  double y[3];
+  int n[3];
+} oc_xf;
+
+static void oc_xf_apply(const oc_xf *t, const double *x, double *o) {
+  for (int q = 0; q < 3; ++q) o[q] = t->R[3 * q] * x[0] + t->R[3 * q + 1] * x[1] + t->R[3 * q + 2] * x[2] + t->y[q];
+}
+
+/* rotation part only (how vectors such as forces and G transform) */
+static void oc_xf_rotate(const oc_xf *t, const double *v, double *o) {
+  for (int q = 0; q < 3; ++q) o[q] = t->R[3 * q] * v[0] + t->R[3 * q + 1] * v[1] + t->R[3 * q + 2] * v[2];
+}
+
+/* o = a after b (x -> a(b(x))) */
+static void oc_xf_compose(const oc_xf *a, const oc_xf *b, oc_xf *o) {
+  oc_xf r;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j)
+      r.R[3 * i + j] = a->R[3 * i] * b->R[j] + a->R[3 * i + 1] * b->R[3 + j] + a->R[3 * i + 2] * b->R[6 + j];
+    r.y[i] = a->R[3 * i] * b->y[0] + a->R[3 * i + 1] * b->y[1] + a->R[3 * i + 2] * b->y[2] + a->y[i];
+  }
+  for (int k = 0; k < 3; ++k) r.n[k] = 0;
+  *o = r;
+}
+
+static void oc_xf_identity(oc_xf *t) {
+  for (int i = 0; i < 9; ++i) t->R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  for (int q = 0; q < 3; ++q) {
+    t->y[q] = 0.0;
+    t->n[q] = 0;
+  }
+}
+
+static int oc_xf_is_identity(const oc_xf *t, double scale) {
+  for (int i = 0; i < 9; ++i)
+    if (fabs(t->R[i] - ((i % 4 == 0) ? 1.0 : 0.0)) > 1e-12) return 0;
+  for (int q = 0; q < 3; ++q)
+    if (fabs(t->y[q]) > 1e-9 * scale) return 0;
+  return 1;
+}
+
+/* Generator k as a transform (rot NULL: the identity rotation). */
+static void oc_generator(const double *lat, const double *rot, int k, int inverse, oc_xf *t) {
+  oc_xf_identity(t);
+  if (rot)
+    for (int i = 0; i < 9; ++i) t->R[i] = rot[9 * k + i];
+  for (int q = 0; q < 3; ++q) t->y[q] = lat[3 * k + q];
+  if (inverse) { /* x = R^T (x' - y) */
+    oc_xf v;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) v.R[3 * i + j] = t->R[3 * j + i];
+    for (int i = 0; i < 3; ++i) v.y[i] = -(v.R[3 * i] * t->y[0] + v.R[3 * i + 1] * t->y[1] + v.R[3 * i + 2] * t->y[2]);
+    for (int q = 0; q < 3; ++q) v.n[q] = 0;
+    *t = v;
+  }
+}
+
+/* Image sets.  span 0: every image the forces need (translations to ceil(rc/|y|), rotations over their
+ * whole finite group); span 1: powers in {-1,0,1} (the cell pairs); span 2: translations to +-2 and
+ * rotations over their whole group (used to look for images beyond the first).  Returns the count, or
+ * -1 for an invalid set of generators. */
+static int oc_transforms(int nper, const double *lat, const double *rot, double rc, int span, oc_xf *out, int maxn) {
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  double scale = 1.0;
+  for (int k = 0; k < nper; ++k) scale += fabs(lat[3 * k]) + fabs(lat[3 * k + 1]) + fabs(lat[3 * k + 2]);
   for (int k = 0; k < nper; ++k) {
-    double len = sqrt(lat[3 * k] * lat[3 * k] + lat[3 * k + 1] * lat[3 * k + 1] + lat[3 * k + 2] * lat[3 * k + 2]);
-    if (!(len > 0)) return -1;
-    m[k] = (int)ceil(rc / len);
-    for (int l = 0; l < k; ++l) {
-      double dot = lat[3 * k] * lat[3 * l] + lat[3 * k + 1] * lat[3 * l + 1] + lat[3 * k + 2] * lat[3 * l + 2];
-      if (fabs(dot) > 1e-12 * len * len) return -1; /* orthogonal lattices only */
+    oc_xf g;
+    oc_generator(lat, rot, k, 0, &g);
+    int is_rot = 0;
+    for (int i = 0; i < 9; ++i)
+      if (g.R[i] != ((i % 4 == 0) ? 1.0 : 0.0)) is_rot = 1;
+    if (is_rot) {
+      /* orthonormal with determinant +1 */
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double d = g.R[3 * i] * g.R[3 * j] + g.R[3 * i + 1] * g.R[3 * j + 1] + g.R[3 * i + 2] * g.R[3 * j + 2];
+          if (fabs(d - (i == j ? 1.0 : 0.0)) > 1e-12) return -1;
+        }
+      double det = g.R[0] * (g.R[4] * g.R[8] - g.R[5] * g.R[7]) - g.R[1] * (g.R[3] * g.R[8] - g.R[5] * g.R[6]) +
+                   g.R[2] * (g.R[3] * g.R[7] - g.R[4] * g.R[6]);
+      if (!(det > 0)) return -1;
+      oc_xf p = g;
+      int K = 1;
+      while (!oc_xf_is_identity(&p, scale)) {
+        if (++K > 64) return -1; /* not of finite order */
+        oc_xf_compose(&g, &p, &p);
+      }
+      if (span == 1) {
+        lo[k] = -1;
+        hi[k] = 1;
+      } else {
+        lo[k] = -((K - 1) / 2);
+        hi[k] = K / 2;
+      }
+    } else {
+      double len = sqrt(lat[3 * k] * lat[3 * k] + lat[3 * k + 1] * lat[3 * k + 1] + lat[3 * k + 2] * lat[3 * k + 2]);
+      if (!(len > 0)) return -1;
+      int m = span == 0 ? (int)ceil(rc / len) : span;
+      lo[k] = -m;
+      hi[k] = m;
+      for (int l = 0; l < k; ++l) {
+        double dot = lat[3 * k] * lat[3 * l] + lat[3 * k + 1] * lat[3 * l + 1] + lat[3 * k + 2] * lat[3 * l + 2];
+        int l_rot = 0;
+        if (rot)
+          for (int i = 0; i < 9; ++i)
+            if (rot[9 * l + i] != ((i % 4 == 0) ? 1.0 : 0.0)) l_rot = 1;
+        if (!l_rot && fabs(dot) > 1e-12 * len * len) return -1; /* orthogonal translations only */
+      }
     }
   }
+  /* the generators must commute */
+  for (int k = 0; k < nper; ++k)
+    for (int l = 0; l < k; ++l) {
+      oc_xf a, b, ab, ba;
+      oc_generator(lat, rot, k, 0, &a);
+      oc_generator(lat, rot, l, 0, &b);
+      oc_xf_compose(&a, &b, &ab);
+      oc_xf_compose(&b, &a, &ba);
+      for (int i = 0; i < 9; ++i)
+        if (fabs(ab.R[i] - ba.R[i]) > 1e-12) return -1;
+      for (int q = 0; q < 3; ++q)
+        if (fabs(ab.y[q] - ba.y[q]) > 1e-9 * scale) return -1;
+    }
   int cnt = 0;
-  for (int a = -m[0]; a <= m[0]; ++a)
-    for (int b = -m[1]; b <= m[1]; ++b)
-      for (int c = -m[2]; c <= m[2]; ++c) {
+  for (int a = lo[0]; a <= hi[0]; ++a)
+    for (int b = lo[1]; b <= hi[1]; ++b)
+      for (int c = lo[2]; c <= hi[2]; ++c) {
         int n[3] = {a, b, c};
         if (cnt >= maxn) return -1;
-        for (int q = 0; q < 3; ++q) {
-          img[3 * cnt + q] = 0.0;
-          code[3 * cnt + q] = n[q];
+        oc_xf t;
+        oc_xf_identity(&t);
+        for (int k = 0; k < nper; ++k) {
+          oc_xf g;
+          oc_generator(lat, rot, k, n[k] < 0, &g);
+          for (int r = 0; r < abs(n[k]); ++r) oc_xf_compose(&g, &t, &t);
         }
-        for (int k = 0; k < nper; ++k)
-          for (int q = 0; q < 3; ++q) img[3 * cnt + q] += n[k] * lat[3 * k + q];
-        ++cnt;
+        for (int q = 0; q < 3; ++q) t.n[q] = n[q];
+        out[cnt++] = t;
       }
+  /* distinct images only (a generator power must not equal another image) */
+  for (int i = 0; i < cnt; ++i)
+    for (int j = 0; j < i; ++j) {
+      int same = 1;
+      for (int e = 0; e < 9 && same; ++e)
+        if (fabs(out[i].R[e] - out[j].R[e]) > 1e-12) same = 0;
+      for (int q = 0; q < 3 && same; ++q)
+        if (fabs(out[i].y[q] - out[j].y[q]) > 1e-9 * scale) same = 0;
+      if (same) return -1;
+    }
   return cnt;
 }
 
+static int oc_is_zero(const int *n) { return n[0] == 0 && n[1] == 0 && n[2] == 0; }
+
 #define OC_MAXIMG 4096
+static oc_xf *oc_images_for(int nper, const double *lat, const double *rot, double rc, int span, int *count) {
+  oc_xf *t = (oc_xf *)malloc(sizeof(oc_xf) * OC_MAXIMG);
+  *count = oc_transforms(nper, lat, rot, rc, span, t, OC_MAXIMG);
+  if (*count < 0) {
+    free(t);
+    return NULL;
+  }
+  return t;
+}
 
 /* ------------------------------------------------------------------ forces, energy, virial */
 
 /* Row a collects sum over b, n with (b,n) != (a,0) and s < rc^2 of F_ab; U and W
  * collect half of each term per row (every pair is seen from both rows). */
 static void oc_row(int64_t a, int64_t n, const double *x, const int32_t *sp, const double *eps, const double *sig,
-                   double rc2, int nimg, const double *img, double *Fa, double *Ua, double *Wa, int64_t *npa) {
+                   double rc2, int nimg, const oc_xf *img, double *Fa, double *Ua, double *Wa, int64_t *npa) {
   double f0 = 0, f1 = 0, f2 = 0, u2 = 0, w2 = 0;
   int64_t cnt = 0;
   for (int64_t b = 0; b < n; ++b) {
     double e, sg;
     oc_mix(eps, sig, sp[a], sp[b], &e, &sg);
     for (int k = 0; k < nimg; ++k) {
-      if (b == a && img[3 * k] == 0 && img[3 * k + 1] == 0 && img[3 * k + 2] == 0) continue;
-      double d0 = x[3 * a] - (x[3 * b] + img[3 * k]);
-      double d1 = x[3 * a + 1] - (x[3 * b + 1] + img[3 * k + 1]);
-      double d2 = x[3 * a + 2] - (x[3 * b + 2] + img[3 * k + 2]);
+      if (b == a && oc_is_zero(img[k].n)) continue;
+      double xb[3];
+      oc_xf_apply(&img[k], x + 3 * b, xb);
+      double d0 = x[3 * a] - xb[0];
+      double d1 = x[3 * a + 1] - xb[1];
+      double d2 = x[3 * a + 2] - xb[2];
       double s = d0 * d0 + d1 * d1 + d2 * d2;
       if (s < rc2) {
         double u, g;
@@ -123,11 +269,15 @@ static void oc_row(int64_t a, int64_t n, const double *x, const int32_t *sp, con
 }
 
 int oc_forces(int64_t n, const double *x, const int32_t *sp, int32_t nsp, const double *eps, const double *sig,
-              double rc, int32_t nper, const double *lat, double *F, double *U, double *W, int64_t *npairs) {
-  static double img[3 * OC_MAXIMG];
-  static int code[3 * OC_MAXIMG];
-  int nimg = oc_images(nper, lat, rc, img, code, OC_MAXIMG);
-  if (nimg < 0 || n < 0 || nsp < 1) return OC_E_INVAL;
+              double rc, int32_t nper, const double *lat, const double *rot, double *F, double *U, double *W,
+              int64_t *npairs) {
+  int nimg;
+  oc_xf *img = oc_images_for(nper, lat, rot, rc, 0, &nimg);
+  if (!img) return OC_E_INVAL;
+  if (n < 0 || nsp < 1) {
+    free(img);
+    return OC_E_INVAL;
+  }
   double *Ur = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
   double *Wr = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
   int64_t *Cr = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
@@ -147,60 +297,81 @@ int oc_forces(int64_t n, const double *x, const int32_t *sp, int32_t nsp, const 
   free(Ur);
   free(Wr);
   free(Cr);
+  free(img);
   return OC_OK;
 }
 
 /* Forces on selected rows only (each against all n molecules): the sampled
  * check for workloads too large for all pairs.  Urow/Wrow/cnt are per-row half sums. */
 int oc_forces_rows(int64_t n, const double *x, const int32_t *sp, int32_t nsp, const double *eps, const double *sig,
-                   double rc, int32_t nper, const double *lat, int64_t nrows, const int64_t *rows, double *F,
-                   double *Urow, double *Wrow, int64_t *cnt) {
-  static double img[3 * OC_MAXIMG];
-  static int code[3 * OC_MAXIMG];
-  int nimg = oc_images(nper, lat, rc, img, code, OC_MAXIMG);
-  if (nimg < 0 || nsp < 1) return OC_E_INVAL;
+                   double rc, int32_t nper, const double *lat, const double *rot, int64_t nrows,
+                   const int64_t *rows, double *F, double *Urow, double *Wrow, int64_t *cnt) {
+  int nimg;
+  oc_xf *img = oc_images_for(nper, lat, rot, rc, 0, &nimg);
+  if (!img) return OC_E_INVAL;
+  if (nsp < 1) {
+    free(img);
+    return OC_E_INVAL;
+  }
   double rc2 = rc * rc;
 #pragma omp parallel for schedule(static)
   for (int64_t r = 0; r < nrows; ++r) oc_row(rows[r], n, x, sp, eps, sig, rc2, nimg, img, F + 3 * r, Urow + r, Wrow + r, cnt + r);
+  free(img);
   return OC_OK;
 }
 
-/* Pair set: every unordered pair {a, b+image} with s < rc^2, reported as
- * (a, b, n) with a < b and d = x_a - x_b - sum_k n_k v_k.  Returns the count;
- * arrays may be NULL to count only. */
-int64_t oc_pairs(int64_t n, const double *x, double rc, int32_t nper, const double *lat, int64_t cap, int32_t *pa,
-                 int32_t *pb, int8_t *pn) {
-  static double img[3 * OC_MAXIMG];
-  static int code[3 * OC_MAXIMG];
-  int nimg = oc_images(nper, lat, rc, img, code, OC_MAXIMG);
-  if (nimg < 0) return -1;
+/* Pair set: every unordered pair {a, T_n b} with s < rc^2, reported as
+ * (a, b, n) with a < b (or a == b and n lexicographically positive: a molecule
+ * and its own image) and d = x_a - T_n x_b.  Returns the count; arrays may be
+ * NULL to count only. */
+int64_t oc_pairs(int64_t n, const double *x, double rc, int32_t nper, const double *lat, const double *rot,
+                 int64_t cap, int32_t *pa, int32_t *pb, int8_t *pn) {
+  int nimg;
+  oc_xf *img = oc_images_for(nper, lat, rot, rc, 0, &nimg);
+  if (!img) return -1;
   double rc2 = rc * rc;
   int64_t cnt = 0;
   for (int64_t a = 0; a < n; ++a)
-    for (int64_t b = a + 1; b < n; ++b)
+    for (int64_t b = a; b < n; ++b)
       for (int k = 0; k < nimg; ++k) {
-        double d0 = x[3 * a] - (x[3 * b] + img[3 * k]);
-        double d1 = x[3 * a + 1] - (x[3 * b + 1] + img[3 * k + 1]);
-        double d2 = x[3 * a + 2] - (x[3 * b + 2] + img[3 * k + 2]);
+        const int *nk = img[k].n;
+        if (b == a) { /* n lexicographically positive */
+          int pos = 0;
+          for (int q = 0; q < 3; ++q) {
+            if (nk[q] > 0) {
+              pos = 1;
+              break;
+            }
+            if (nk[q] < 0) break;
+          }
+          if (!pos) continue;
+        }
+        double xb[3];
+        oc_xf_apply(&img[k], x + 3 * b, xb);
+        double d0 = x[3 * a] - xb[0];
+        double d1 = x[3 * a + 1] - xb[1];
+        double d2 = x[3 * a + 2] - xb[2];
         double s = d0 * d0 + d1 * d1 + d2 * d2;
         if (s < rc2) {
           if (pa && cnt < cap) {
             pa[cnt] = (int32_t)a;
             pb[cnt] = (int32_t)b;
-            pn[3 * cnt] = (int8_t)code[3 * k];
-            pn[3 * cnt + 1] = (int8_t)code[3 * k + 1];
-            pn[3 * cnt + 2] = (int8_t)code[3 * k + 2];
+            pn[3 * cnt] = (int8_t)nk[0];
+            pn[3 * cnt + 1] = (int8_t)nk[1];
+            pn[3 * cnt + 2] = (int8_t)nk[2];
           }
           ++cnt;
         }
       }
+  free(img);
   return cnt;
 }
 
 /* ------------------------------------------------------------------ adjoint */
 
-/* L = sum_i G_i . F_i + gamma U.  Per pair (a,b,image) with d = x_a - x_b', s = d.d:
- *   l = (G_a - G_b).d g(s) + gamma u(s)
+/* L = sum_i G_i . F_i + gamma U.  Per pair (a, b, image T) with d = x_a - T x_b, s = d.d, and the
+ * image's G rotated with it, G_b' = R G_b (a force on the image acts on b rotated back by R^T):
+ *   l = (G_a - G_b').d g(s) + gamma u(s)
  *   dl/dd = g (G_a-G_b) + [2 g'(s) ((G_a-G_b).d) - gamma g] d      (du/ds = -g/2)
  *   dl/deps_ab = l / eps_ab
  *   dl/dsig_ab = ((G_a-G_b).d) dg/dsig + gamma du/dsig
@@ -211,15 +382,19 @@ int64_t oc_pairs(int64_t n, const double *x, double rc, int32_t nper, const doub
  *   d eps_ab/d eps_a = eps_ab/(2 eps_a) (a != b), 1 (a == b);
  *   d sig_ab/d sig_a = 1/2 (a != b), 1 (a == b).
  * The cut-off radius is absolute, so sigma does not move it.
- * Row a collects dL/dx_a = sum_b dl/dd(a,b) (each pair seen from both rows, with
- * dl/dd symmetric under a<->b, d -> -d); parameter sums take half per row. */
+ * Row a collects dL/dx_a = sum_b dl/dd(a,b) (each pair seen from both rows: from b's row the pair is
+ * (b, a, T^-1) with d and G_a - G_b' both mapped by -R^T, and dl/dd maps the same way, so that row's
+ * term is the gradient with respect to x_b); parameter sums take half per row. */
 int oc_adjoint(int64_t n, const double *x, const int32_t *sp, int32_t nsp, const double *eps, const double *sig,
-               double rc, int32_t nper, const double *lat, const double *G, double gamma, double *gx, double *geps,
-               double *gsig, double *L) {
-  static double img[3 * OC_MAXIMG];
-  static int code[3 * OC_MAXIMG];
-  int nimg = oc_images(nper, lat, rc, img, code, OC_MAXIMG);
-  if (nimg < 0 || nsp < 1 || nsp > 8) return OC_E_INVAL;
+               double rc, int32_t nper, const double *lat, const double *rot, const double *G, double gamma,
+               double *gx, double *geps, double *gsig, double *L) {
+  int nimg;
+  oc_xf *img = oc_images_for(nper, lat, rot, rc, 0, &nimg);
+  if (!img) return OC_E_INVAL;
+  if (nsp < 1 || nsp > 8) {
+    free(img);
+    return OC_E_INVAL;
+  }
   double rc2 = rc * rc;
   /* per-row partial sums for the species-pair parameter gradients and L */
   double *pe = (double *)calloc((size_t)(n > 0 ? n : 1) * 64, sizeof(double));
@@ -231,12 +406,15 @@ int oc_adjoint(int64_t n, const double *x, const int32_t *sp, int32_t nsp, const
     for (int64_t b = 0; b < n; ++b) {
       double e, sg;
       oc_mix(eps, sig, sp[a], sp[b], &e, &sg);
-      double dg0 = G[3 * a] - G[3 * b], dg1 = G[3 * a + 1] - G[3 * b + 1], dg2 = G[3 * a + 2] - G[3 * b + 2];
       for (int k = 0; k < nimg; ++k) {
-        if (b == a && img[3 * k] == 0 && img[3 * k + 1] == 0 && img[3 * k + 2] == 0) continue;
-        double d0 = x[3 * a] - (x[3 * b] + img[3 * k]);
-        double d1 = x[3 * a + 1] - (x[3 * b + 1] + img[3 * k + 1]);
-        double d2 = x[3 * a + 2] - (x[3 * b + 2] + img[3 * k + 2]);
+        if (b == a && oc_is_zero(img[k].n)) continue;
+        double xb[3], gb[3];
+        oc_xf_apply(&img[k], x + 3 * b, xb);
+        oc_xf_rotate(&img[k], G + 3 * b, gb);
+        double dg0 = G[3 * a] - gb[0], dg1 = G[3 * a + 1] - gb[1], dg2 = G[3 * a + 2] - gb[2];
+        double d0 = x[3 * a] - xb[0];
+        double d1 = x[3 * a + 1] - xb[1];
+        double d2 = x[3 * a + 2] - xb[2];
         double s = d0 * d0 + d1 * d1 + d2 * d2;
         if (!(s < rc2)) continue;
         double sr2 = sg * sg / s, sr6 = sr2 * sr2 * sr2, sr12 = sr6 * sr6;
@@ -297,6 +475,7 @@ int oc_adjoint(int64_t n, const double *x, const int32_t *sp, int32_t nsp, const
   free(pe);
   free(ps);
   free(pl);
+  free(img);
   return OC_OK;
 }
 
@@ -537,34 +716,55 @@ static double tri_tri2(const double *A, const double *B) {
   return best;
 }
 
-/* Is the closest distance between cell c and cell d translated by T below R? */
-static int oc_cells_in_range(const oc_cell *C, const oc_cell *D, const double *T, double R) {
+/* Cell D mapped by the referring transform t: its vertices, triangles and bounding box (the caller
+ * frees out->v and out->tri). */
+static void oc_cell_mapped(const oc_cell *D, const oc_xf *t, oc_cell *out) {
+  out->nv = D->nv;
+  out->ntri = D->ntri;
+  out->v = (double *)malloc(sizeof(double) * 3 * (D->nv > 0 ? D->nv : 1));
+  out->tri = (double *)malloc(sizeof(double) * 9 * (D->ntri > 0 ? D->ntri : 1));
+  for (int j = 0; j < D->nv; ++j) oc_xf_apply(t, D->v + 3 * j, out->v + 3 * j);
+  for (int j = 0; j < 3 * D->ntri; ++j) oc_xf_apply(t, D->tri + 3 * j, out->tri + 3 * j);
+  oc_xf_apply(t, D->cen, out->cen);
+  for (int q = 0; q < 3; ++q) {
+    out->lo[q] = 1e300;
+    out->hi[q] = -1e300;
+  }
+  for (int j = 0; j < D->nv; ++j)
+    for (int q = 0; q < 3; ++q) {
+      if (out->v[3 * j + q] < out->lo[q]) out->lo[q] = out->v[3 * j + q];
+      if (out->v[3 * j + q] > out->hi[q]) out->hi[q] = out->v[3 * j + q];
+    }
+}
+
+static void oc_cell_unmap(oc_cell *c) {
+  free(c->v);
+  free(c->tri);
+}
+
+/* Is the closest distance between cell c and the (already mapped) cell d below R? */
+static int oc_cells_in_range(const oc_cell *C, const oc_cell *D, double R) {
   double R2 = R * R;
   /* bounding boxes farther apart than R: not in range */
   double g2 = 0;
   for (int q = 0; q < 3; ++q) {
-    double lo = D->lo[q] + T[q], hi = D->hi[q] + T[q];
     double gap = 0;
-    if (lo > C->hi[q]) gap = lo - C->hi[q];
-    if (C->lo[q] > hi) gap = C->lo[q] - hi;
+    if (D->lo[q] > C->hi[q]) gap = D->lo[q] - C->hi[q];
+    if (C->lo[q] > D->hi[q]) gap = C->lo[q] - D->hi[q];
     g2 += gap * gap;
   }
   if (g2 >= R2) return 0;
   /* a vertex pair closer than R: in range */
   for (int i = 0; i < C->nv; ++i)
     for (int j = 0; j < D->nv; ++j) {
-      double d[3] = {C->v[3 * i] - D->v[3 * j] - T[0], C->v[3 * i + 1] - D->v[3 * j + 1] - T[1],
-                     C->v[3 * i + 2] - D->v[3 * j + 2] - T[2]};
+      double d[3];
+      sub3(C->v + 3 * i, D->v + 3 * j, d);
       if (dot3(d, d) < R2) return 1;
     }
   /* full minimum over boundary triangle pairs */
-  double Bt[9];
   for (int i = 0; i < C->ntri; ++i)
-    for (int j = 0; j < D->ntri; ++j) {
-      for (int k = 0; k < 3; ++k)
-        for (int q = 0; q < 3; ++q) Bt[3 * k + q] = D->tri[9 * j + 3 * k + q] + T[q];
-      if (tri_tri2(C->tri + 9 * i, Bt) < R2) return 1;
-    }
+    for (int j = 0; j < D->ntri; ++j)
+      if (tri_tri2(C->tri + 9 * i, D->tri + 9 * j) < R2) return 1;
   return 0;
 }
 
@@ -582,39 +782,42 @@ static int oc_mesh_from(int64_t n_points, const double *points, int64_t n_faces,
   return OC_OK;
 }
 
-/* Exact closest distance between cell c and cell d shifted by T (for pins). */
+/* Exact closest distance between cell c and cell d mapped by x -> Rm x + T (Rm NULL: the identity),
+ * for pins. */
 double oc_cell_distance(int64_t n_points, const double *points, int64_t n_faces, const int64_t *face_off,
                         const int32_t *face_pts, const int32_t *owner, const int32_t *neighbour, int64_t n_cells,
-                        int32_t c, int32_t d, const double *T) {
+                        int32_t c, int32_t d, const double *T, const double *Rm) {
   oc_mesh m;
   oc_mesh_from(n_points, points, n_faces, face_off, face_pts, owner, neighbour, n_cells, &m);
   oc_cell *cells;
   if (oc_build_cells(&m, &cells) != OC_OK) return -1;
-  double best = 1e300, Bt[9];
-  oc_cell *C = &cells[c], *D = &cells[d];
+  oc_xf t;
+  oc_xf_identity(&t);
+  for (int q = 0; q < 3; ++q) t.y[q] = T[q];
+  if (Rm)
+    for (int i = 0; i < 9; ++i) t.R[i] = Rm[i];
+  oc_cell Dm;
+  oc_cell_mapped(&cells[d], &t, &Dm);
+  double best = 1e300;
+  oc_cell *C = &cells[c];
   for (int i = 0; i < C->ntri; ++i)
-    for (int j = 0; j < D->ntri; ++j) {
-      for (int k = 0; k < 3; ++k)
-        for (int q = 0; q < 3; ++q) Bt[3 * k + q] = D->tri[9 * j + 3 * k + q] + T[q];
-      double t = tri_tri2(C->tri + 9 * i, Bt);
-      if (t < best) best = t;
+    for (int j = 0; j < Dm.ntri; ++j) {
+      double v = tri_tri2(C->tri + 9 * i, Dm.tri + 9 * j);
+      if (v < best) best = v;
     }
+  oc_cell_unmap(&Dm);
   oc_free_cells(cells, n_cells);
   return sqrt(best);
 }
 
-/* Brute-force interacting cell pairs: every (c, d, n) with closest distance
- * between cell c and cell d + sum_k n_k v_k below rc + guard, n_k in {-1,0,1},
- * reported once: c < d, or c == d with n lexicographically positive.  Returns
- * the count (arrays may be NULL to count only), or <0 on error. */
-/* The paper's own cell-pair predicate (Sec. 2.2, App. A.1): some vertex of c and some vertex of d + T
- * are closer than R.  Brute force over all vertex pairs. */
-static int oc_vertices_in_range(const oc_cell *c, const oc_cell *d, const double *T, double R) {
+/* The paper's own cell-pair predicate (Sec. 2.2, App. A.1): some vertex of c and some vertex of the
+ * mapped cell d are closer than R.  Brute force over all vertex pairs. */
+static int oc_vertices_in_range(const oc_cell *c, const oc_cell *d, double R) {
   for (int i = 0; i < c->nv; ++i)
     for (int j = 0; j < d->nv; ++j) {
       double s = 0;
       for (int q = 0; q < 3; ++q) {
-        double e = c->v[3 * i + q] - (d->v[3 * j + q] + T[q]);
+        double e = c->v[3 * i + q] - d->v[3 * j + q];
         s += e * e;
       }
       if (s < R * R) return 1;
@@ -622,29 +825,32 @@ static int oc_vertices_in_range(const oc_cell *c, const oc_cell *d, const double
   return 0;
 }
 
-/* Interacting cell pairs, canonical (c < d, or c == d with the lattice image lexicographically
- * positive).  predicate 0: closest distance between the closed cells below rc + guard; 1: the paper's
- * vertex-to-vertex distance below rc + guard. */
+/* Brute-force interacting cell pairs: every (c, d, n) with the closest distance
+ * between cell c and cell d mapped by image n (powers in {-1,0,1}) below
+ * rc + guard (predicate 0), or some vertex pair closer than that (predicate 1,
+ * the paper's test), reported once: c < d, or c == d with n lexicographically
+ * positive.  Returns the count (arrays may be NULL to count only), or <0 on
+ * error. */
 int64_t oc_dil(int64_t n_points, const double *points, int64_t n_faces, const int64_t *face_off,
                const int32_t *face_pts, const int32_t *owner, const int32_t *neighbour, int64_t n_cells,
-               int32_t nper, const double *lat, double rc, double guard, int32_t predicate, int64_t cap, int32_t *oc,
-               int32_t *od, int8_t *on) {
+               int32_t nper, const double *lat, const double *rot, double rc, double guard, int32_t predicate,
+               int64_t cap, int32_t *oc, int32_t *od, int8_t *on) {
   oc_mesh m;
   oc_mesh_from(n_points, points, n_faces, face_off, face_pts, owner, neighbour, n_cells, &m);
-  oc_cell *cells;
-  if (oc_build_cells(&m, &cells) != OC_OK) return OC_E_MESH;
   double R = rc + guard;
-  int nimg = 1;
-  for (int k = 0; k < nper; ++k) nimg *= 3;
+  int nimg;
+  oc_xf *img = oc_images_for(nper, lat, rot, R, 1, &nimg);
+  if (!img) return OC_E_INVAL;
+  oc_cell *cells;
+  if (oc_build_cells(&m, &cells) != OC_OK) {
+    free(img);
+    return OC_E_MESH;
+  }
   int64_t cnt = 0;
   for (int64_t c = 0; c < n_cells; ++c)
     for (int64_t d = c; d < n_cells; ++d)
       for (int im = 0; im < nimg; ++im) {
-        int n[3] = {0, 0, 0}, r = im;
-        for (int k = 0; k < nper; ++k) {
-          n[k] = r % 3 - 1;
-          r /= 3;
-        }
+        const int *n = img[im].n;
         if (c == d) {
           /* keep n lexicographically > 0 only (n = 0 is the cell itself) */
           int pos = 0;
@@ -657,11 +863,11 @@ int64_t oc_dil(int64_t n_points, const double *points, int64_t n_faces, const in
           }
           if (!pos) continue;
         }
-        double T[3] = {0, 0, 0};
-        for (int k = 0; k < nper; ++k)
-          for (int q = 0; q < 3; ++q) T[q] += n[k] * lat[3 * k + q];
-        if (predicate == 1 ? oc_vertices_in_range(&cells[c], &cells[d], T, R)
-                           : oc_cells_in_range(&cells[c], &cells[d], T, R)) {
+        oc_cell Dm;
+        oc_cell_mapped(&cells[d], &img[im], &Dm);
+        const int hit = predicate == 1 ? oc_vertices_in_range(&cells[c], &Dm, R) : oc_cells_in_range(&cells[c], &Dm, R);
+        oc_cell_unmap(&Dm);
+        if (hit) {
           if (oc && cnt < cap) {
             oc[cnt] = (int32_t)c;
             od[cnt] = (int32_t)d;
@@ -671,6 +877,40 @@ int64_t oc_dil(int64_t n_points, const double *points, int64_t n_faces, const in
         }
       }
   oc_free_cells(cells, n_cells);
+  free(img);
+  return cnt;
+}
+
+/* Cell pairs (c, d, n), any order, in range (closest distance below rc + guard) through an image with
+ * some power outside {-1,0,1}: translations to +-2, rotations over their whole group.  Zero means the
+ * first images suffice (the referred-cell lists with powers in {-1,0,1} are complete). */
+int64_t oc_far_images(int64_t n_points, const double *points, int64_t n_faces, const int64_t *face_off,
+                      const int32_t *face_pts, const int32_t *owner, const int32_t *neighbour, int64_t n_cells,
+                      int32_t nper, const double *lat, const double *rot, double rc, double guard) {
+  oc_mesh m;
+  oc_mesh_from(n_points, points, n_faces, face_off, face_pts, owner, neighbour, n_cells, &m);
+  double R = rc + guard;
+  int nimg;
+  oc_xf *img = oc_images_for(nper, lat, rot, R, 2, &nimg);
+  if (!img) return OC_E_INVAL;
+  oc_cell *cells;
+  if (oc_build_cells(&m, &cells) != OC_OK) {
+    free(img);
+    return OC_E_MESH;
+  }
+  int64_t cnt = 0;
+  for (int im = 0; im < nimg; ++im) {
+    const int *n = img[im].n;
+    if (abs(n[0]) <= 1 && abs(n[1]) <= 1 && abs(n[2]) <= 1) continue;
+    for (int64_t d = 0; d < n_cells; ++d) {
+      oc_cell Dm;
+      oc_cell_mapped(&cells[d], &img[im], &Dm);
+      for (int64_t c = 0; c < n_cells; ++c) cnt += oc_cells_in_range(&cells[c], &Dm, R);
+      oc_cell_unmap(&Dm);
+    }
+  }
+  oc_free_cells(cells, n_cells);
+  free(img);
   return cnt;
 }
 

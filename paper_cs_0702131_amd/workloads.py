@@ -6,8 +6,10 @@ path and the FP64 oracle consume, so that the two sides see identical data.
 Meshes use a face-based polyhedral description (the static unstructured mesh
 of Sec. 2.3): points, faces as vertex loops (normal out of the owner cell by
 the right-hand rule), owner and neighbour cell per face (neighbour -1 on a
-boundary), and a set of periodic lattice vectors.  Cell indices can be
-shuffled, since a cell's index says nothing about where it is (Sec. 2.3).
+boundary), and the referring transforms of the periodic directions: x -> R x + y
+with y in `periodic` and R in `rotations` (None: every R = I, plain lattice
+translations).  Cell indices can be shuffled, since a cell's index says nothing
+about where it is (Sec. 2.3).
 
 All positions and box lengths are rounded to multiples of Q = 2**-15 so that
 differences of coordinates below 512 sigma are exact in FP32 and FP64.
@@ -35,9 +37,10 @@ class Mesh:
     owner: np.ndarray           # [F] i32
     neighbour: np.ndarray       # [F] i32, -1 for boundary faces
     n_cells: int
-    periodic: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))  # [k,3] lattice vectors
+    periodic: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))  # [k,3] transform shifts y_k
     lo: np.ndarray = None       # domain bounding box (for fixtures)
     hi: np.ndarray = None
+    rotations: np.ndarray = None  # [k,3,3] transform rotations R_k, or None for lattice translations
 
     @property
     def n_faces(self):
@@ -110,7 +113,8 @@ def renumber_cells(m: Mesh, new_of_old):
     owner = new_of_old[m.owner].astype(np.int32)
     neighbour = np.where(m.neighbour >= 0, new_of_old[np.maximum(m.neighbour, 0)], -1).astype(np.int32)
     out = Mesh(points=m.points, face_off=m.face_off, face_pts=m.face_pts, owner=owner,
-               neighbour=neighbour, n_cells=m.n_cells, periodic=m.periodic, lo=m.lo, hi=m.hi)
+               neighbour=neighbour, n_cells=m.n_cells, periodic=m.periodic, lo=m.lo, hi=m.hi,
+               rotations=m.rotations)
     return out
 
 
@@ -140,7 +144,7 @@ def delete_cells(m: Mesh, kill):
                face_pts=np.concatenate(new_loops).astype(np.int32) if new_loops else np.zeros(0, np.int32),
                owner=keep_idx[new_owner[sel]].astype(np.int32),
                neighbour=np.where(new_nei[sel] >= 0, keep_idx[np.maximum(new_nei[sel], 0)], -1).astype(np.int32),
-               n_cells=int((~kill).sum()), periodic=m.periodic, lo=m.lo, hi=m.hi)
+               n_cells=int((~kill).sum()), periodic=m.periodic, lo=m.lo, hi=m.hi, rotations=m.rotations)
     return out
 
 
@@ -168,7 +172,8 @@ def jitter_interior(m: Mesh, xs, ys, zs, amp, rng):
     du = rng.uniform(-1.0, 1.0, size=pts.shape) * amp * h
     pts[interior] += du[interior]
     out = Mesh(points=pts, face_off=m.face_off, face_pts=m.face_pts, owner=m.owner,
-               neighbour=m.neighbour, n_cells=m.n_cells, periodic=m.periodic, lo=m.lo, hi=m.hi)
+               neighbour=m.neighbour, n_cells=m.n_cells, periodic=m.periodic, lo=m.lo, hi=m.hi,
+               rotations=m.rotations)
     out.shape = getattr(m, "shape", None)
     return out
 
@@ -334,6 +339,10 @@ class Workload:
     @property
     def lattice(self):
         return self.mesh.periodic
+
+    @property
+    def rotations(self):
+        return self.mesh.rotations
 
 
 def _rng(k, child):
@@ -584,3 +593,121 @@ def config3(seed=3, n_cells_target=6.0e5, post_r=8.0):
     v *= np.sqrt(3.0 * N * 1.0 / (v ** 2).sum())
     return Workload(f"posts{N}_channel200x60x60", mesh, x, np.zeros(N, np.int32), np.array([1.0]), np.array([1.0]),
                     2.5, lo, hi, (0, 2), extra={"v": v, "posts": posts, "post_r": post_r})
+
+
+# ----------------------------------------------------------------------------------------------
+# rotationally periodic sector (referring transforms with a rotation, Sec. 2.2.2)
+
+
+def rot_z(angle):
+    """Rotation by `angle` about the z axis."""
+    c, s = math.cos(angle), math.sin(angle)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def wedge_mesh(r0, r1, n_sectors, Lz, nr, nphi, nz, jitter, rng, shuffle=True):
+    """Hex mesh of one sector (angle 2 pi / n_sectors) of the annulus r0 <= r <= r1, 0 <= z < Lz.
+
+    Nodes at (r_i cos phi_j, r_i sin phi_j, z_k) on a uniform (r, phi, z) grid, interior nodes moved by
+    U(-jitter h, jitter h) in (r, phi, z) before the mapping (faces stay planar on the boundary, so the
+    sector is bounded by planes through the z axis, chords of the two walls and two z planes).  The
+    sides phi = 0 and phi = 2 pi / n_sectors are coupled by the rotation about z, z by the translation
+    Lz; the walls r = r0, r1 are plain boundaries."""
+    theta = 2.0 * math.pi / n_sectors
+    rs = np.linspace(r0, r1, nr + 1)
+    ps = np.linspace(0.0, theta, nphi + 1)
+    zs = uniform_nodes(Lz, nz)
+    m = hex_mesh(rs, ps, zs)
+    if jitter > 0:
+        m = jitter_interior(m, rs, ps, zs, jitter, rng)
+    r, p, z = m.points[:, 0], m.points[:, 1], m.points[:, 2]
+    # exact node values on the two coupled sides, so that one is the rotation of the other
+    p = np.where(np.isclose(p, 0.0, atol=1e-15), 0.0, p)
+    pts = np.stack([r * np.cos(p), r * np.sin(p), z], axis=1)
+    side = np.isclose(m.points[:, 1], theta, rtol=0, atol=1e-13)
+    pts[side] = (rot_z(theta) @ np.stack([r[side], np.zeros(side.sum()), z[side]], axis=0)).T
+    out = Mesh(points=pts, face_off=m.face_off, face_pts=m.face_pts, owner=m.owner, neighbour=m.neighbour,
+               n_cells=m.n_cells, periodic=np.array([[0.0, 0.0, 0.0], [0.0, 0.0, Lz]]),
+               lo=np.array([0.0, 0.0, 0.0]), hi=np.array([r1, r1, Lz]),
+               rotations=np.stack([rot_z(theta), np.eye(3)]))
+    out.wedge = dict(r0=r0, r1=r1, n_sectors=n_sectors, theta=theta, Lz=Lz, nr=nr, nphi=nphi, nz=nz)
+    if shuffle:
+        out2 = renumber_cells(out, rng.permutation(out.n_cells))
+        out2.wedge = out.wedge
+        out = out2
+    return out
+
+
+def wedge_images(x, n_sectors, Lz, copies=1):
+    """Positions of the rotated (powers -copies..copies of the sector rotation) and z-shifted (-1, 0, 1)
+    copies of x, with the power pairs: input preparation for minimum-separation checks."""
+    theta = 2.0 * math.pi / n_sectors
+    out, tags = [], []
+    for a in range(-copies, copies + 1):
+        Ra = rot_z(a * theta)
+        for b in (-1, 0, 1):
+            out.append(x @ Ra.T + np.array([0.0, 0.0, b * Lz]))
+            tags.append((a, b))
+    return out, tags
+
+
+def wedge_positions(mesh, density, jitter, rng, margin=1e-3):
+    """Molecules on rings: z layers and radii at spacing h = density^(-1/3), on each ring
+    floor(r theta / h) sites evenly spread over (0, theta), each moved by U(-jitter, jitter) per axis.
+    Radii run from r0 + h/2 to the chord of the outer wall less h/2, so every site is inside the mesh;
+    sites next to the coupled sides sit half a spacing from them."""
+    w = mesh.wedge
+    theta, Lz = w["theta"], w["Lz"]
+    dphi = theta / w["nphi"]
+    h = density ** (-1.0 / 3.0)
+    rin, rout = w["r0"] + 0.5 * h, w["r1"] * math.cos(0.5 * dphi) - 0.5 * h
+    nrad = int(math.floor((rout - rin) / h)) + 1
+    nzl = max(1, int(round(Lz / h)))
+    sites = []
+    for i in range(nrad):
+        r = rin + i * h
+        m = max(1, int(math.floor(r * theta / h)))
+        p = (np.arange(m) + 0.5) * (theta / m)
+        for k in range(nzl):
+            z = (k + 0.25 + 0.5 * (i % 2)) * (Lz / nzl)
+            sites.append(np.stack([r * np.cos(p), r * np.sin(p), np.full(m, z)], axis=1))
+    x = np.vstack(sites)
+    x = x + rng.uniform(-jitter, jitter, size=x.shape)
+    # stay inside: radial range and the two sides (the jitter is far below h / 2)
+    x = qround(x)
+    x[:, 2] = np.mod(x[:, 2], Lz)
+    return x
+
+
+def wedge(seed=6, r0=10.0, r1=22.0, n_sectors=12, Lz=8.0, nr=10, nphi=8, nz=6, density=0.7, jitter=0.2):
+    """Molecules in a rotationally periodic annular sector (12 sectors of 30 degrees by default), periodic
+    in z, walls at r0 and r1; ring-lattice sites at the given density, jittered by +-0.1."""
+    rng = _rng(seed, 0)
+    mesh = wedge_mesh(r0, r1, n_sectors, qround(Lz), nr, nphi, nz, jitter, rng)
+    x = wedge_positions(mesh, density, 0.1, _rng(seed, 1))
+    n = len(x)
+    return Workload(f"wedge{n}_sector{n_sectors}_r{r0:g}-{r1:g}", mesh, x, np.zeros(n, np.int32), np.array([1.0]),
+                    np.array([1.0]), 2.5, mesh.lo, mesh.hi, (), extra={"wedge": mesh.wedge})
+
+
+def annulus_from_wedge(mesh, x, G=None):
+    """The whole annulus: n_sectors rotated copies of the sector mesh (as disjoint cell sets) and of the
+    positions (and of per-molecule vectors G), periodic in z only.  Copy s of molecule i is s * N + i."""
+    w = mesh.wedge
+    K, theta = w["n_sectors"], w["theta"]
+    P, F = len(mesh.points), mesh.n_faces
+    pts, fo, fp, ow, ne, xs, gs = [], [0], [], [], [], [], []
+    for s in range(K):
+        Rs = rot_z(s * theta)
+        pts.append(mesh.points @ Rs.T)
+        fo.extend((mesh.face_off[1:] + fo[-1]).tolist())
+        fp.append(mesh.face_pts + s * P)
+        ow.append(mesh.owner + s * mesh.n_cells)
+        ne.append(np.where(mesh.neighbour >= 0, mesh.neighbour + s * mesh.n_cells, -1))
+        xs.append(x @ Rs.T)
+        if G is not None:
+            gs.append(np.asarray(G) @ Rs.T)
+    full = Mesh(points=np.vstack(pts), face_off=np.array(fo, np.int64), face_pts=np.concatenate(fp).astype(np.int32),
+                owner=np.concatenate(ow).astype(np.int32), neighbour=np.concatenate(ne).astype(np.int32),
+                n_cells=K * mesh.n_cells, periodic=np.array([[0.0, 0.0, w["Lz"]]]))
+    return full, np.vstack(xs), (np.vstack(gs) if G is not None else None)

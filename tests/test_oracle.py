@@ -368,3 +368,182 @@ def test_nve_energy_error_scales_dt2(oracle):
     s2 = _verlet_energy_span(oracle, wl.x, lat, 0.002, int(T / 0.002))
     ratio = s1 / s2
     assert 3.2 < ratio < 4.8, ratio
+
+
+# ---------------------------------------------------------------- rotational referral (Sec. 2.2.2)
+#
+# Pins of the referring transform with a rotation: the paper's formula for R against the plane
+# rotation about z built from cos / sin, and the sector oracle (images under the sector rotation and
+# the z translation) against the whole annulus assembled from rotated copies and evaluated with z
+# translations only, so that no rotation of the oracle enters the reference side.
+
+
+def _boundary_face_normals(mesh, pred):
+    """Unit outward normals and centres of the boundary faces whose centre satisfies pred."""
+    out = []
+    for f in range(mesh.n_faces):
+        if mesh.neighbour[f] >= 0:
+            continue
+        loop = mesh.face_pts[mesh.face_off[f]:mesh.face_off[f + 1]]
+        P = mesh.points[loop]
+        c = P.mean(0)
+        if not pred(c):
+            continue
+        n = np.cross(P[1] - P[0], P[2] - P[0])
+        out.append((n / np.linalg.norm(n), c))
+    return out
+
+
+def test_referring_transform_formula(oracle):
+    # antiparallel normals (a plain periodic boundary): R = I, y = C_b - C_a
+    R, y = oracle.referring_transform([1, 0, 0], [-1, 0, 0], [5.0, 1, 2], [0.0, 1, 2])
+    assert np.allclose(R, np.eye(3), atol=1e-15) and np.allclose(y, [-5, 0, 0], atol=1e-15)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        na, nb = rng.standard_normal(3), rng.standard_normal(3)
+        na, nb = na / np.linalg.norm(na), nb / np.linalg.norm(nb)
+        R, y = oracle.referring_transform(na, nb, rng.standard_normal(3), rng.standard_normal(3))
+        assert np.allclose(R @ -na, nb, atol=1e-13)                    # -n_a onto n_b
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-13)             # orthogonal
+        assert abs(np.linalg.det(R) - 1.0) < 1e-13                      # proper rotation
+        ax = np.cross(na, nb)                                           # the axis stays put
+        assert np.allclose(R @ ax, ax, atol=1e-13)
+    # the wedge's coupled sides: outward normals of the faces on phi = 0 and on phi = theta
+    m = W.wedge_mesh(10.0, 22.0, 12, 8.0, 3, 2, 2, 0.0, np.random.default_rng(0), shuffle=False)
+    th = m.wedge["theta"]
+    side0 = _boundary_face_normals(m, lambda c: abs(c[1]) < 1e-9)
+    side1 = _boundary_face_normals(m, lambda c: abs(c[1] - math.tan(th) * c[0]) < 1e-9 and c[1] > 1e-9)
+    assert len(side0) == len(side1) == 3 * 2
+    Rz = W.rot_z(th)
+    for (na, ca) in side0:
+        # the coupled face: the one whose centre is the rotated centre
+        nb, cb = min(side1, key=lambda t: np.linalg.norm(t[1] - Rz @ ca))
+        R, y = oracle.referring_transform(na, nb, ca, cb)
+        assert np.allclose(R, Rz, atol=1e-13)
+        assert np.allclose(y, 0.0, atol=1e-12)
+        assert np.allclose(y + R @ ca, cb, atol=1e-12)   # the face centre goes to the coupled centre
+    # re-referring: two sector rotations compose to the rotation by 2 theta; with a z shift as well
+    R2, y2 = oracle.compose_transforms((Rz, np.zeros(3)), (Rz, np.array([0.0, 0.0, 8.0])))
+    assert np.allclose(R2, W.rot_z(2 * th), atol=1e-14) and np.allclose(y2, [0, 0, 8.0])
+    p = np.array([12.0, 1.0, 3.0])
+    assert np.allclose(y2 + R2 @ p, Rz @ (Rz @ p) + [0, 0, 8.0], atol=1e-13)
+
+
+@pytest.fixture(scope="module")
+def wedge_small():
+    return W.wedge()
+
+
+def test_wedge_forces_equal_whole_annulus(oracle, wedge_small):
+    w = wedge_small
+    K = w.mesh.wedge["n_sectors"]
+    F, U, Wv, npairs = oracle.forces(w.x, w.species, w.eps, w.sigma, w.rcut, w.lattice, rot=w.rotations)
+    full, xf, _ = W.annulus_from_wedge(w.mesh, w.x)
+    Ff, Uf, Wf, nf = oracle.forces(xf, np.zeros(len(xf), np.int32), w.eps, w.sigma, w.rcut, full.periodic)
+    n = w.n
+    assert npairs > 10 * n // 2 and nf == K * npairs
+    assert abs(Uf - K * U) <= 1e-11 * abs(Uf)
+    assert abs(Wf - K * Wv) <= 1e-11 * abs(Wf)
+    scale = np.sqrt(np.mean(F ** 2))
+    assert np.max(np.abs(Ff[:n] - F)) <= 1e-11 * scale
+    # every copy carries the rotated forces
+    for s in (1, 5):
+        Rs = W.rot_z(s * w.mesh.wedge["theta"])
+        assert np.max(np.abs(Ff[s * n:(s + 1) * n] - F @ Rs.T)) <= 1e-11 * scale
+    # the sector sees molecules across both coupled sides (otherwise the check above is vacuous)
+    pr = oracle.pairs(w.x, w.rcut, w.lattice, rot=w.rotations)
+    assert (pr[:, 2] == 1).sum() > 20 and (pr[:, 2] == -1).sum() > 20
+
+
+def test_wedge_torque_and_axial_force_vanish(oracle, wedge_small):
+    # rotation about z and translation along z leave (x cross F)_z and F_z of every pair balanced
+    w = wedge_small
+    F, U, Wv, npairs = oracle.forces(w.x, w.species, w.eps, w.sigma, w.rcut, w.lattice, rot=w.rotations)
+    scale = np.abs(F).sum()
+    tz = (w.x[:, 0] * F[:, 1] - w.x[:, 1] * F[:, 0]).sum()
+    assert abs(tz) <= 1e-12 * scale * 22.0
+    assert abs(F[:, 2].sum()) <= 1e-12 * scale
+    # while the in-plane net force need not vanish (the system is not translation invariant in x, y)
+    assert abs(F[:, 0].sum()) > 1e-6 * scale
+
+
+def test_wedge_adjoint_equals_whole_annulus(oracle, wedge_small):
+    w = wedge_small
+    K = w.mesh.wedge["n_sectors"]
+    G = np.random.default_rng(5).standard_normal((w.n, 3))
+    gx, ge, gs, L = oracle.adjoint(w.x, w.species, w.eps, w.sigma, w.rcut, w.lattice, G, 0.3, rot=w.rotations)
+    full, xf, Gf = W.annulus_from_wedge(w.mesh, w.x, G)
+    gxf, gef, gsf, Lf = oracle.adjoint(xf, np.zeros(len(xf), np.int32), w.eps, w.sigma, w.rcut, full.periodic,
+                                       Gf, 0.3)
+    assert abs(Lf - K * L) <= 1e-11 * abs(Lf)
+    assert abs(gef[0] - K * ge[0]) <= 1e-11 * abs(gef[0])
+    assert abs(gsf[0] - K * gs[0]) <= 1e-11 * abs(gsf[0])
+    assert np.max(np.abs(gxf[:w.n] - gx)) <= 1e-11 * np.sqrt(np.mean(gx ** 2))
+    # L itself: sum G.F + gamma U from the forces
+    F, U, _, _ = oracle.forces(w.x, w.species, w.eps, w.sigma, w.rcut, w.lattice, rot=w.rotations)
+    assert abs(L - (np.sum(G * F) + 0.3 * U)) <= 1e-12 * (abs(L) + abs(U))
+
+
+def test_wedge_pairs_map_to_annulus_pairs(oracle, wedge_small):
+    w = wedge_small
+    K, n = w.mesh.wedge["n_sectors"], w.n
+    pr = oracle.pairs(w.x, w.rcut, w.lattice, rot=w.rotations)
+    full, xf, _ = W.annulus_from_wedge(w.mesh, w.x)
+    pf = oracle.pairs(xf, w.rcut, full.periodic)
+    assert len(pf) == K * len(pr)
+    # pair (s_a N + a, s_b N + b, z) is the sector pair (a, b) through rotation power s_b - s_a (mod K)
+    sa, a = np.divmod(pf[:, 0], n)
+    sb, b = np.divmod(pf[:, 1], n)
+    rp = np.mod(sb - sa + K // 2, K) - K // 2
+    assert np.all(np.abs(rp) <= 1)
+    mapped = oracle.canonical_pairs(a, b, np.stack([rp, pf[:, 2], np.zeros_like(rp)], axis=1))
+    uniq, cnt = np.unique(mapped, axis=0, return_counts=True)
+    assert np.all(cnt == K)
+    assert np.array_equal(uniq, pr)
+
+
+def test_wedge_dil_equals_annulus_dil(oracle):
+    m = W.wedge_mesh(10.0, 16.0, 12, 6.0, 4, 3, 3, 0.2, np.random.default_rng(7))
+    K = m.wedge["n_sectors"]
+    rc, guard = 2.5, 1e-6 * 2.5
+    dil = oracle.dil(m, rc, guard)
+    full, _, _ = W.annulus_from_wedge(m, np.zeros((0, 3)))
+    dfull = oracle.dil(full, rc, guard)
+    nc = m.n_cells
+    assert len(dfull) == K * len(dil)
+    sc, c = np.divmod(dfull[:, 0], nc)
+    sd, d = np.divmod(dfull[:, 1], nc)
+    rp = np.mod(sd - sc + K // 2, K) - K // 2
+    assert np.all(np.abs(rp) <= 1)
+    mapped = oracle.canonical_pairs(c, d, np.stack([rp, dfull[:, 2], np.zeros_like(rp)], axis=1))
+    uniq, cnt = np.unique(mapped, axis=0, return_counts=True)
+    assert np.all(cnt == K)
+    assert np.array_equal(uniq, dil)
+    assert (dil[:, 2] != 0).sum() > 0
+    # the first powers suffice here; near the axis they do not
+    assert oracle.far_images(m, rc, guard) == 0
+    narrow = W.wedge_mesh(1.5, 6.0, 8, 6.0, 3, 2, 3, 0.0, np.random.default_rng(1))
+    assert oracle.far_images(narrow, rc, guard) > 0
+
+
+def test_invalid_referring_transforms(oracle):
+    x = np.array([[11.0, 1.0, 1.0], [12.0, 1.5, 2.0]])
+    lat = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 8.0]])
+    ok = np.stack([W.rot_z(math.pi / 6), np.eye(3)])
+    oracle.forces(x, [0, 0], [1.0], [1.0], 2.5, lat, rot=ok)
+    bad = [np.stack([W.rot_z(1.0), np.eye(3)]),                      # infinite order
+           np.stack([W.rot_z(math.pi / 6) * 1.01, np.eye(3)]),       # not orthogonal
+           np.stack([np.diag([1.0, 1.0, -1.0]), np.eye(3)])]          # a reflection
+    for r in bad:
+        with pytest.raises(ValueError):
+            oracle.forces(x, [0, 0], [1.0], [1.0], 2.5, lat, rot=r)
+    # a half turn is its own inverse: its group {I, T} is summed once for the forces, but the cell
+    # pairs through powers -1 and 1 would list the same image twice
+    half = np.stack([W.rot_z(math.pi), np.eye(3)])
+    oracle.forces(x, [0, 0], [1.0], [1.0], 2.5, lat, rot=half)
+    m = W.wedge_mesh(10.0, 16.0, 2, 6.0, 2, 2, 2, 0.0, np.random.default_rng(1))
+    with pytest.raises(ValueError):
+        oracle.dil(m, 2.5, 0.0)
+    # rotation about z with a translation along x: the two do not commute
+    with pytest.raises(ValueError):
+        oracle.forces(x, [0, 0], [1.0], [1.0], 2.5, np.array([[0.0, 0, 0], [30.0, 0, 0]]), rot=ok)
