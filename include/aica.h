@@ -6,10 +6,13 @@
  * cells of a static, unstructured, arbitrary polyhedral mesh (Sec. 2.2, 2.3).
  * Each cell interacts with itself and with the cells on its direct
  * interaction list (DIL), every cell pair being listed once (Sec. 2.2,
- * App. A.1); periodic boundaries are handled by referred cells, i.e.
- * translated images of real cells (Sec. 2.1, 2.2.1, 2.2.2).  On one GPU only
- * periodic referral exists, so every referring transform is a lattice
- * translation (R = I in the referring-result equation of Sec. 2.2.2).
+ * App. A.1); periodic boundaries are handled by referred cells, i.e. images
+ * of real cells under the boundary's referring transform (Sec. 2.1, 2.2.1,
+ * 2.2.2).  On one GPU only periodic referral exists; each periodic direction
+ * has one transform in the generic form P' = y + R.P of Sec. 2.2.2: a lattice
+ * translation (R = I) or a rotation about an axis (coupled boundaries that
+ * are not parallel, e.g. the two sides of a sector of a rotationally
+ * symmetric domain).
  *
  * Conventions for every call:
  *   - Return value: AICA_OK (0) or a negative AICA_E_* code; nothing throws.
@@ -55,7 +58,13 @@ typedef struct aica_mesh {
   const int32_t *neighbour;  /* [n_faces] other cell, or -1 on a boundary face */
   int64_t n_cells;
   int32_t n_periodic;        /* number of periodic directions (0..3) */
-  double periodic_vec[3][3]; /* mutually orthogonal lattice translations of the periodic directions */
+  double periodic_vec[3][3]; /* y_k: the shift of direction k's referring transform x -> R_k x + y_k */
+  const double *periodic_rot;/* NULL (every R_k = I: lattice translations, which must be mutually
+                                orthogonal), or [n_periodic][3][3] row-major R_k.  A rotation (R_k != I)
+                                must be proper (orthonormal, det +1) and of finite order K_k <= 64 with
+                                K_k >= 3 (T_k^K = identity; T_k and its inverse distinct), and the
+                                transforms of all directions must commute.  Image n of a cell is
+                                T_1^n_1 T_2^n_2 T_3^n_3 with n_k in {-1, 0, 1}. */
 } aica_mesh;
 
 /* Lennard-Jones model and evaluation options.  Host memory. */
@@ -73,10 +82,14 @@ typedef struct aica_dil aica_dil;  /* opaque handle */
 
 /* Setup (Sec. 2.3 and App. A): validate the mesh, build every cell's direct
  * interaction list and the periodic referred-cell pairs, once.  A cell pair
- * (c, d, t), t a lattice translation with components in {-1,0,1}, is listed
- * when the closest distance between cell c and cell d translated by t is
- * below rcut + guard; each pair is listed once (App. A.1), and no cell is
- * listed with itself at t = 0.  Cell geometry: each face is fanned into
+ * (c, d, n), n the image powers with components in {-1,0,1}, is listed when
+ * the closest distance between cell c and cell d mapped by image n is below
+ * rcut + guard; each pair is listed once (App. A.1: (c, d, n) and (d, c, -n)
+ * are the same pair), and no cell is listed with itself at n = 0.  Images
+ * beyond the first powers must be out of range: for lattice translations
+ * rcut + guard must be below half of every periodic length, and with a
+ * rotation no cell pair may be in range through any other power of the
+ * transforms (checked; AICA_E_RCUT otherwise).  Cell geometry: each face is fanned into
  * triangles around the mean of its vertices; the cell is the union of the
  * tetrahedra (cell vertex mean, face triangle), all of which must have
  * positive volume.  rcut > 0 is the largest cut-off of any potential
@@ -115,8 +128,9 @@ int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, v
 
 /* Per-step forces (Sec. 2.3.1 real-real and 2.3.2 real-referred loops, with
  * the reaction -F applied to the partner, Sec. 2.2): for every unordered pair
- * {a, b + image} with |d|^2 < rcut^2, d = x_a - x_b - t,
- *   u = 4 eps_ab [(sigma_ab/r)^12 - (sigma_ab/r)^6],  F_a += g d, F_b -= g d,
+ * {a, T b} (T the image's referring transform x -> R x + y) with
+ * |d|^2 < rcut^2, d = x_a - T x_b,
+ *   u = 4 eps_ab [(sigma_ab/r)^12 - (sigma_ab/r)^6],  F_a += g d, F_b -= R^T g d,
  *   g = 24 eps_ab [2 sigma_ab^12 r^-14 - sigma_ab^6 r^-8],
  *   U = sum u, W = sum g |d|^2 (virial sum r.F), npairs = number of pairs.
  * pos_dev must be the array last passed to aica_bin (same pointer, dtype and
@@ -127,8 +141,10 @@ int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, v
  * overwritten.  Either may be NULL.  Results are deterministic (fixed
  * summation order, no atomics on forces).  With AICA_FP32 the cut-off is still
  * decided exactly for positions that are multiples of 2^-15 (pairs within
- * 2^-20 rc^2 of rc^2 are decided in FP64).  Errors: AICA_E_INVAL, AICA_E_NOMEM,
- * AICA_E_HIP. */
+ * 2^-20 rc^2 of rc^2 are decided in FP64), except for images with a rotation:
+ * their referred positions are rounded to FP32 after the rotation, so a pair
+ * within about 1e-6 rc of the cut-off may be decided either way.
+ * Errors: AICA_E_INVAL, AICA_E_NOMEM, AICA_E_HIP. */
 int aica_forces(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
                 void *forces_dev, double *uw_dev, int64_t *npairs_dev, void *hip_stream);
 
@@ -149,12 +165,13 @@ int aica_forces_adjoint(aica_dil *dil, const void *pos_dev, const int32_t *speci
 /* ---- diagnostics (tests and benchmarks) ---- */
 
 /* The interacting cell pairs in mesh cell ids: (c, d, img) with c < d, or
- * c == d and img lexicographically positive; img[3] holds the multiples of
- * the periodic vectors.  Host arrays.  With c == NULL only *n is set. */
+ * c == d and img lexicographically positive; img[3] holds the powers of the
+ * periodic directions' transforms.  Host arrays.  With c == NULL only *n is set. */
 int aica_dil_export(const aica_dil *dil, int64_t *n, int32_t *c, int32_t *d, int8_t *img);
 
 /* The molecule pairs the GPU path evaluates inside the cut-off, as (a, b, img)
- * with a < b and d = x_a - x_b - sum_k img_k v_k.  Runs the same traversal as
+ * with d = x_a - T_img x_b (a and b in either order; a == b for a molecule and
+ * its own image).  Runs the same traversal as
  * aica_forces after aica_bin.  Host output arrays of capacity cap; *n gets the
  * count (which may exceed cap: call again with a larger cap). */
 int aica_pairs_export(aica_dil *dil, const void *pos_dev, const aica_params *params, int64_t cap, int64_t *n,

@@ -46,6 +46,10 @@ class DIL:
         for k in range(len(per)):
             for q in range(3):
                 m.periodic_vec[k][q] = per[k, q]
+        rot = getattr(mesh, "rotations", None)
+        if rot is not None:  # referring transforms x -> R_k x + y_k (kept alive until the call returns)
+            rot = np.ascontiguousarray(np.asarray(rot, dtype=np.float64).reshape(len(per), 3, 3))
+            m.periodic_rot = rot.ctypes.data
         h = C.c_void_p()
         pred = {"closest": _lib.AICA_DIL_CLOSEST, "vertex": _lib.AICA_DIL_VERTEX}[predicate]
         check(lib().aica_build_dil_ex(C.byref(m), self.rcut, self.guard, pred, C.byref(h)))

@@ -40,7 +40,7 @@ class aica_mesh(C.Structure):
     _fields_ = [("n_points", C.c_int64), ("points", C.c_void_p), ("n_faces", C.c_int64),
                 ("face_off", C.c_void_p), ("face_pts", C.c_void_p), ("owner", C.c_void_p),
                 ("neighbour", C.c_void_p), ("n_cells", C.c_int64), ("n_periodic", C.c_int32),
-                ("periodic_vec", (C.c_double * 3) * 3)]
+                ("periodic_vec", (C.c_double * 3) * 3), ("periodic_rot", C.c_void_p)]
 
 
 class aica_params(C.Structure):

@@ -104,6 +104,7 @@ struct aica_dil {
   int64_t groups_for_n = -1;
   Groups grp;
   DBuf d_orig, d_g_cell0, d_e_off, d_e_B, d_e_vec32, d_e_vec64, d_nl_off, d_nl_e, d_nl_d, d_nl_r, d_rcnt;
+  DBuf d_rot64;                 // [27][9] rotation of every image code (only with rotational referral)
   // per step
   bool bin_valid = false;
   bool wsteps_valid = false;  // d_gnp holds the wave-step counts of a forward call on the current binning
@@ -871,18 +872,35 @@ static int ensure_groups(aica_dil *h, int64_t n) {
   const int64_t E = G.e_off[G.ng];
   std::vector<float4> v32(E);
   std::vector<double4> v64(E);
+  // Entry offsets: a j of group B at xm relative to orig_B is referred into A's frame at R xm + o with
+  // o = T(orig_B) - orig_A (R = I and o = orig_B + t - orig_A for a translation).  The fourth component
+  // holds the image code, plus kRotFlag when the image has a rotation (whose R the kernels look up).
   for (int64_t e = 0; e < E; ++e) {
     const int64_t B = G.e_B[e];
     int64_t A = std::upper_bound(G.e_off.begin(), G.e_off.end(), e) - G.e_off.begin() - 1;
+    const Xf T = image_transform(h->geo, G.e_img[3 * e], G.e_img[3 * e + 1], G.e_img[3 * e + 2]);
     double o[3];
-    for (int q = 0; q < 3; ++q) {
-      double t = 0;
-      for (int k = 0; k < h->geo.nper; ++k) t += G.e_img[3 * e + k] * h->geo.per[k][q];
-      o[q] = G.orig[3 * B + q] + t - G.orig[3 * A + q];
+    if (T.rot) {
+      double tb[3];
+      T.apply(&G.orig[3 * B], tb);
+      for (int q = 0; q < 3; ++q) o[q] = tb[q] - G.orig[3 * A + q];
+    } else {
+      for (int q = 0; q < 3; ++q) o[q] = G.orig[3 * B + q] + T.y[q] - G.orig[3 * A + q];
     }
-    const int code = 9 * (G.e_img[3 * e] + 1) + 3 * (G.e_img[3 * e + 1] + 1) + (G.e_img[3 * e + 2] + 1);
+    const int code = 9 * (G.e_img[3 * e] + 1) + 3 * (G.e_img[3 * e + 1] + 1) + (G.e_img[3 * e + 2] + 1) +
+                     (T.rot ? kRotFlag : 0);
     v32[e] = make_float4((float)o[0], (float)o[1], (float)o[2], __builtin_bit_cast(float, code));
     v64[e] = make_double4(o[0], o[1], o[2], __builtin_bit_cast(double, (int64_t)code));
+  }
+  if (h->geo.has_rot) {  // R of every image code (the identity for translations)
+    std::vector<double> r64(27 * 9);
+    for (int code = 0; code < 27; ++code) {
+      const Xf T = image_transform(h->geo, code / 9 - 1, (code / 3) % 3 - 1, code % 3 - 1);
+      for (int i = 0; i < 9; ++i) {
+        r64[9 * code + i] = T.R[i];
+      }
+    }
+    if ((rc = upload(h->d_rot64, r64))) return rc;
   }
   if ((rc = upload(h->d_g_cell0, G.cell0))) return rc;
   if ((rc = upload(h->d_e_off, G.e_off))) return rc;
@@ -1122,14 +1140,27 @@ static int launch_pair(aica_dil *h, const LJTab &tab, const AdjTab &at, bool com
   double *gpart = MODE == 0 ? h->d_gpart.as<double>() : (MODE == 2 ? h->d_gpar.as<double>() : nullptr);
   unsigned long long *gnp = MODE == 0 ? h->d_gnp.as<unsigned long long>() : nullptr;
   int32_t *pairs_out = MODE == 1 ? h->d_pairs.as<int32_t>() : nullptr;
+  // rotating referral: FP64 rotations and offsets for both precisions (the referred position is rounded once)
+  const double *rot = h->geo.has_rot ? h->d_rot64.as<double>() : nullptr;
+  const double4 *evd = h->geo.has_rot ? h->d_e_vec64.as<double4>() : nullptr;
   const int nsp = tab.nsp;
-#define AICA_LAUNCH(MIX, COMP)                                                                                     \
-  hipLaunchKernelGGL((k_pair<T, MIX, MODE, COMP>), dim3((unsigned)padded), dim3(64 * NW), 0, st, pos, gs,          \
+#define AICA_LAUNCH_R(MIX, COMP, ROT)                                                                              \
+  hipLaunchKernelGGL((k_pair<T, MIX, MODE, COMP, ROT>), dim3((unsigned)padded), dim3(64 * NW), 0, st, pos, gs,     \
                      h->d_g_start.as<int32_t>(), h->d_g_cell0.as<int32_t>(), h->d_cell_start.as<int32_t>(), ev,    \
                      h->d_slot_base.as<int64_t>(), h->d_nl_off.as<int64_t>(), h->d_nl_e.as<int32_t>(),            \
                      h->d_nl_d.as<int32_t>(), h->d_nl_r.as<int32_t>(), jpart, own, gpart, gnp, ng, padded, tab, at, \
-                     h->d_perm.as<int32_t>(), cap, pairs_out, pcount, h->epoch)
-  if constexpr (MODE == 2) {  // the adjoint supports one or two species
+                     rot, evd, h->d_perm.as<int32_t>(), cap, pairs_out, pcount, h->epoch)
+#define AICA_LAUNCH(MIX, COMP) AICA_LAUNCH_R(MIX, COMP, false)
+  if (rot) {  // rotating referral: compensated sums always (the variants with a rotation are built once)
+    if constexpr (MODE == 2) {
+      if (nsp == 1) AICA_LAUNCH_R(0, true, true);
+      else AICA_LAUNCH_R(1, true, true);
+    } else {
+      if (nsp == 1) AICA_LAUNCH_R(0, true, true);
+      else if (nsp == 2) AICA_LAUNCH_R(1, true, true);
+      else AICA_LAUNCH_R(2, true, true);
+    }
+  } else if constexpr (MODE == 2) {  // the adjoint supports one or two species
     if (nsp == 1) AICA_LAUNCH(0, true);
     else AICA_LAUNCH(1, true);
   } else if (MODE == 1) {
@@ -1146,6 +1177,7 @@ static int launch_pair(aica_dil *h, const LJTab &tab, const AdjTab &at, bool com
     else AICA_LAUNCH(2, false);
   }
 #undef AICA_LAUNCH
+#undef AICA_LAUNCH_R
   HIPCHK(hipGetLastError());
   return AICA_OK;
 }

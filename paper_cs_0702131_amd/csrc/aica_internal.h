@@ -41,6 +41,24 @@ void parallel_for(int64_t n, F f) {
   for (auto &x : th) x.join();
 }
 
+// A referring transform x -> R x + y (the generic form of Sec. 2.2.2); rot == false means R = I.
+struct Xf {
+  double R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  double y[3] = {0, 0, 0};
+  bool rot = false;
+  void apply(const double *x, double *o) const {
+    if (!rot) {
+      for (int q = 0; q < 3; ++q) o[q] = x[q] + y[q];
+      return;
+    }
+    double t[3];
+    for (int q = 0; q < 3; ++q) t[q] = R[3 * q] * x[0] + R[3 * q + 1] * x[1] + R[3 * q + 2] * x[2] + y[q];
+    for (int q = 0; q < 3; ++q) o[q] = t[q];
+  }
+  Xf inverse() const;                 // x = R^T (x' - y)
+  Xf then(const Xf &b) const;         // b after this: x -> b(this(x))
+};
+
 // Host copy of the mesh plus derived cell geometry (Sec. 2.3: static mesh).
 struct Geometry {
   int64_t np = 0, nf = 0, nc = 0;
@@ -49,7 +67,10 @@ struct Geometry {
   std::vector<int32_t> fpts;     // vertex loops
   std::vector<int32_t> own, nei; // [nf]
   int nper = 0;
-  double per[3][3] = {{0}};
+  double per[3][3] = {{0}};      // y_k of each periodic direction's transform
+  Xf gen[3];                     // the transforms T_k themselves
+  int order[3] = {0, 0, 0};      // K_k for a rotation (T_k^K = identity), 0 for a translation
+  bool has_rot = false;          // some direction refers with a rotation
   // derived
   std::vector<double> fcen;      // [nf][3] face vertex mean
   std::vector<int64_t> cf_off;   // [nc+1] faces of each cell
@@ -73,6 +94,9 @@ int build_geometry(const aica_mesh *m, Geometry &g);
 // Spatially coherent cell order (k-d median splits of cell centroids):
 // order[s] = mesh cell at sorted position s; rank[c] = sorted position of mesh cell c.
 void spatial_order(const Geometry &g, std::vector<int32_t> &order, std::vector<int32_t> &rank);
+
+// Image n of the periodic directions: T_1^n0 T_2^n1 T_3^n2 (the transforms commute).
+Xf image_transform(const Geometry &g, int n0, int n1, int n2);
 
 // One interacting cell pair in sorted cell indices: sc < sd, or sc == sd with img > 0 (lexicographic).
 struct CellPair {

@@ -7,6 +7,7 @@
 namespace aica {
 
 constexpr int kRow = 16;        // lanes per rotation row (a DPP row)
+constexpr int kRotFlag = 64;     // added to an entry's image code when its referring transform rotates
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
 

@@ -45,6 +45,115 @@ static inline V3 operator*(V3 a, double s) { return {a.x * s, a.y * s, a.z * s};
 static inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 static inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 
+// ------------------------------------------------------------------ referring transforms
+
+Xf Xf::inverse() const {
+  Xf v;
+  v.rot = rot;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) v.R[3 * i + j] = R[3 * j + i];
+  for (int i = 0; i < 3; ++i) v.y[i] = -(v.R[3 * i] * y[0] + v.R[3 * i + 1] * y[1] + v.R[3 * i + 2] * y[2]);
+  return v;
+}
+
+Xf Xf::then(const Xf &b) const {
+  Xf o;
+  o.rot = rot || b.rot;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j)
+      o.R[3 * i + j] = b.R[3 * i] * R[j] + b.R[3 * i + 1] * R[3 + j] + b.R[3 * i + 2] * R[6 + j];
+    o.y[i] = b.R[3 * i] * y[0] + b.R[3 * i + 1] * y[1] + b.R[3 * i + 2] * y[2] + b.y[i];
+  }
+  return o;
+}
+
+Xf image_transform(const Geometry &g, int n0, int n1, int n2) {
+  const int n[3] = {n0, n1, n2};
+  Xf t;
+  for (int k = 0; k < g.nper; ++k) {
+    const Xf step = n[k] < 0 ? g.gen[k].inverse() : g.gen[k];
+    for (int r = 0; r < std::abs(n[k]); ++r) t = t.then(step);
+  }
+  if (!t.rot)  // a pure translation: keep the exact sum of the lattice vectors
+    for (int q = 0; q < 3; ++q) {
+      t.y[q] = 0;
+      for (int k = 0; k < g.nper; ++k) t.y[q] += n[k] * g.per[k][q];
+    }
+  return t;
+}
+
+static bool same_xf(const Xf &a, const Xf &b, double scale) {
+  for (int i = 0; i < 9; ++i)
+    if (std::fabs(a.R[i] - b.R[i]) > 1e-12) return false;
+  for (int q = 0; q < 3; ++q)
+    if (std::fabs(a.y[q] - b.y[q]) > 1e-9 * scale) return false;
+  return true;
+}
+
+// Validate the periodic directions' transforms (the rules stated with aica_mesh.periodic_rot).
+static int set_transforms(const aica_mesh *m, Geometry &g) {
+  double scale = 1.0;
+  for (int k = 0; k < g.nper; ++k)
+    for (int q = 0; q < 3; ++q) scale += std::fabs(g.per[k][q]);
+  for (int k = 0; k < g.nper; ++k) {
+    Xf &t = g.gen[k];
+    for (int q = 0; q < 3; ++q) t.y[q] = g.per[k][q];
+    if (m->periodic_rot) {
+      for (int i = 0; i < 9; ++i) {
+        t.R[i] = m->periodic_rot[9 * k + i];
+        if (!std::isfinite(t.R[i])) return fail(AICA_E_INVAL, "non-finite periodic rotation");
+        if (t.R[i] != ((i % 4 == 0) ? 1.0 : 0.0)) t.rot = true;
+      }
+    }
+    g.order[k] = 0;
+    if (!t.rot) continue;
+    g.has_rot = true;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double d = t.R[3 * i] * t.R[3 * j] + t.R[3 * i + 1] * t.R[3 * j + 1] + t.R[3 * i + 2] * t.R[3 * j + 2];
+        if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-12) return fail(AICA_E_INVAL, "periodic rotation is not orthonormal");
+      }
+    const double det = t.R[0] * (t.R[4] * t.R[8] - t.R[5] * t.R[7]) - t.R[1] * (t.R[3] * t.R[8] - t.R[5] * t.R[6]) +
+                       t.R[2] * (t.R[3] * t.R[7] - t.R[4] * t.R[6]);
+    if (!(det > 0)) return fail(AICA_E_INVAL, "periodic rotation has determinant -1 (a reflection)");
+    const Xf id;
+    Xf p = t;
+    int K = 1;
+    while (!same_xf(p, id, scale)) {
+      if (++K > 64) return fail(AICA_E_INVAL, "periodic transform with a rotation is not of finite order <= 64");
+      p = p.then(t);
+    }
+    if (K < 3) return fail(AICA_E_INVAL, "periodic transform equals its own inverse (order 2)");
+    g.order[k] = K;
+  }
+  for (int k = 0; k < g.nper; ++k) {
+    const V3 a = mk(g.per[k]);
+    if (!g.gen[k].rot && !(dot(a, a) > 0)) return fail(AICA_E_INVAL, "zero periodic vector");
+    for (int l = 0; l < k; ++l) {
+      const V3 b = mk(g.per[l]);
+      if (!g.gen[k].rot && !g.gen[l].rot && std::fabs(dot(a, b)) > 1e-12 * std::sqrt(dot(a, a) * dot(b, b)))
+        return fail(AICA_E_INVAL, "periodic vectors must be mutually orthogonal");
+      if (!same_xf(g.gen[k].then(g.gen[l]), g.gen[l].then(g.gen[k]), scale))
+        return fail(AICA_E_INVAL, "the periodic transforms do not commute");
+    }
+  }
+  // the first powers must give distinct images
+  int nimg = 1;
+  for (int k = 0; k < g.nper; ++k) nimg *= 3;
+  std::vector<Xf> im;
+  for (int i = 0; i < nimg; ++i) {
+    int n[3] = {0, 0, 0}, r = i;
+    for (int k = 0; k < g.nper; ++k) {
+      n[k] = r % 3 - 1;
+      r /= 3;
+    }
+    im.push_back(image_transform(g, n[0], n[1], n[2]));
+    for (int j = 0; j < i; ++j)
+      if (same_xf(im[i], im[j], scale)) return fail(AICA_E_INVAL, "two periodic images coincide");
+  }
+  return AICA_OK;
+}
+
 // ------------------------------------------------------------------ geometry
 
 int build_geometry(const aica_mesh *m, Geometry &g) {
@@ -60,14 +169,12 @@ int build_geometry(const aica_mesh *m, Geometry &g) {
   g.nper = m->n_periodic;
   for (int k = 0; k < 3; ++k)
     for (int q = 0; q < 3; ++q) g.per[k][q] = k < g.nper ? m->periodic_vec[k][q] : 0.0;
-  for (int k = 0; k < g.nper; ++k) {
-    V3 a = mk(g.per[k]);
-    if (!(dot(a, a) > 0)) return fail(AICA_E_INVAL, "zero periodic vector");
-    for (int l = 0; l < k; ++l) {
-      V3 b = mk(g.per[l]);
-      if (std::fabs(dot(a, b)) > 1e-12 * std::sqrt(dot(a, a) * dot(b, b)))
-        return fail(AICA_E_INVAL, "periodic vectors must be mutually orthogonal");
-    }
+  for (int k = 0; k < g.nper; ++k)
+    for (int q = 0; q < 3; ++q)
+      if (!std::isfinite(g.per[k][q])) return fail(AICA_E_INVAL, "non-finite periodic vector");
+  {
+    const int rc = set_transforms(m, g);
+    if (rc) return rc;
   }
   g.pts.assign(m->points, m->points + 3 * g.np);
   for (double v : g.pts)
@@ -344,16 +451,22 @@ struct CellTris {
   std::vector<double> bb;  // 6 per triangle: lo, hi
 };
 
-static void cell_triangles(const Geometry &g, int32_t c, const V3 &T, CellTris &out) {
+static inline V3 mapped(const Xf &T, const double *p) {
+  double o[3];
+  T.apply(p, o);
+  return mk(o);
+}
+
+static void cell_triangles(const Geometry &g, int32_t c, const Xf &T, CellTris &out) {
   out.t.clear();
   out.bb.clear();
   for (int64_t k = g.cf_off[c]; k < g.cf_off[c + 1]; ++k) {
     int32_t f = g.cf[k];
-    V3 fc = mk(&g.fcen[3 * (int64_t)f]) + T;
+    V3 fc = mapped(T, &g.fcen[3 * (int64_t)f]);
     int64_t b0 = g.foff[f], len = g.foff[f + 1] - b0;
     for (int64_t j = 0; j < len; ++j) {
-      V3 a = mk(&g.pts[3 * (int64_t)g.fpts[b0 + j]]) + T;
-      V3 b = mk(&g.pts[3 * (int64_t)g.fpts[b0 + (j + 1) % len]]) + T;
+      V3 a = mapped(T, &g.pts[3 * (int64_t)g.fpts[b0 + j]]);
+      V3 b = mapped(T, &g.pts[3 * (int64_t)g.fpts[b0 + (j + 1) % len]]);
       out.t.push_back(fc);
       out.t.push_back(a);
       out.t.push_back(b);
@@ -384,22 +497,47 @@ struct CellBox {
   double lo[3], hi[3], cen[3], rin, rout;
 };
 
+// Bounding box of box [lo, hi] mapped by T (the box itself for a translation).
+static inline void mapped_box(const Xf &T, const double *lo, const double *hi, double *mlo, double *mhi) {
+  if (!T.rot) {
+    for (int q = 0; q < 3; ++q) {
+      mlo[q] = lo[q] + T.y[q];
+      mhi[q] = hi[q] + T.y[q];
+    }
+    return;
+  }
+  for (int q = 0; q < 3; ++q) {
+    mlo[q] = 1e300;
+    mhi[q] = -1e300;
+  }
+  for (int k = 0; k < 8; ++k) {
+    const double p[3] = {(k & 1) ? hi[0] : lo[0], (k & 2) ? hi[1] : lo[1], (k & 4) ? hi[2] : lo[2]};
+    double o[3];
+    T.apply(p, o);
+    for (int q = 0; q < 3; ++q) {
+      mlo[q] = std::min(mlo[q], o[q]);
+      mhi[q] = std::max(mhi[q], o[q]);
+    }
+  }
+}
+
 // Cheap classification: 1 = in range, 0 = not, -1 = undecided (needs the exact test).
-static inline int quick_range(const CellBox &C, const CellBox &D, const V3 &T, double R) {
+static inline int quick_range(const CellBox &C, const CellBox &D, const Xf &T, double R) {
   const double R2 = R * R;
   double g2 = 0;
-  const double Tq[3] = {T.x, T.y, T.z};
+  double dlo[3], dhi[3], dc[3];
+  mapped_box(T, D.lo, D.hi, dlo, dhi);
   for (int q = 0; q < 3; ++q) {
-    const double lo = D.lo[q] + Tq[q], hi = D.hi[q] + Tq[q];
     double gap = 0;
-    if (lo > C.hi[q]) gap = lo - C.hi[q];
-    if (C.lo[q] > hi) gap = C.lo[q] - hi;
+    if (dlo[q] > C.hi[q]) gap = dlo[q] - C.hi[q];
+    if (C.lo[q] > dhi[q]) gap = C.lo[q] - dhi[q];
     g2 += gap * gap;
   }
   if (g2 >= R2) return 0;
   // balls of radius r_in about the centroids lie inside the cells (upper bound on the distance);
   // balls of radius r_out contain them (lower bound)
-  const double d0 = C.cen[0] - D.cen[0] - Tq[0], d1 = C.cen[1] - D.cen[1] - Tq[1], d2 = C.cen[2] - D.cen[2] - Tq[2];
+  T.apply(D.cen, dc);
+  const double d0 = C.cen[0] - dc[0], d1 = C.cen[1] - dc[1], d2 = C.cen[2] - dc[2];
   const double cd = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
   if (cd - C.rin - D.rin < R) return 1;
   if (cd - C.rout - D.rout >= R) return 0;
@@ -407,33 +545,41 @@ static inline int quick_range(const CellBox &C, const CellBox &D, const V3 &T, d
 }
 
 // Exact test (after quick_range returned -1): vertex pairs, then boundary triangle pairs.
-static bool cells_in_range(const Geometry &g, int32_t c, int32_t d, const V3 &T, double R, CellTris &tc,
+static bool cells_in_range(const Geometry &g, int32_t c, int32_t d, const Xf &T, double R, CellTris &tc,
                            CellTris &td) {
   const double R2 = R * R;
-  double dlo[3] = {g.lo[3 * (int64_t)d] + T.x, g.lo[3 * (int64_t)d + 1] + T.y, g.lo[3 * (int64_t)d + 2] + T.z};
-  double dhi[3] = {g.hi[3 * (int64_t)d] + T.x, g.hi[3 * (int64_t)d + 1] + T.y, g.hi[3 * (int64_t)d + 2] + T.z};
+  // d's vertices mapped by T (they span its convex hull, which holds the cell)
+  std::vector<V3> &dv = td.t;
+  dv.clear();
+  double dlo[3] = {1e300, 1e300, 1e300}, dhi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t j = g.cv_off[d]; j < g.cv_off[d + 1]; ++j) {
+    const V3 b = mapped(T, &g.pts[3 * (int64_t)g.cv[j]]);
+    dv.push_back(b);
+    const double bq[3] = {b.x, b.y, b.z};
+    for (int q = 0; q < 3; ++q) {
+      dlo[q] = std::min(dlo[q], bq[q]);
+      dhi[q] = std::max(dhi[q], bq[q]);
+    }
+  }
   // separating axis along the centroid direction: every cell lies in the convex hull of its vertices,
   // so a projection gap of at least R proves the cells are out of range
   {
-    V3 u = (mk(&g.ccen[3 * (int64_t)d]) + T) - mk(&g.ccen[3 * (int64_t)c]);
+    V3 u = mapped(T, &g.ccen[3 * (int64_t)d]) - mk(&g.ccen[3 * (int64_t)c]);
     const double uu = std::sqrt(dot(u, u));
     if (uu > 0) {
       u = u * (1.0 / uu);
       double cmax = -1e300, dmin = 1e300;
       for (int64_t i = g.cv_off[c]; i < g.cv_off[c + 1]; ++i) cmax = std::max(cmax, dot(mk(&g.pts[3 * (int64_t)g.cv[i]]), u));
-      for (int64_t j = g.cv_off[d]; j < g.cv_off[d + 1]; ++j)
-        dmin = std::min(dmin, dot(mk(&g.pts[3 * (int64_t)g.cv[j]]) + T, u));
+      for (const V3 &b : dv) dmin = std::min(dmin, dot(b, u));
       if (dmin - cmax >= R * (1.0 + 1e-12)) return false;
     }
   }
   for (int64_t i = g.cv_off[c]; i < g.cv_off[c + 1]; ++i) {
     V3 a = mk(&g.pts[3 * (int64_t)g.cv[i]]);
-    for (int64_t j = g.cv_off[d]; j < g.cv_off[d + 1]; ++j) {
-      V3 b = mk(&g.pts[3 * (int64_t)g.cv[j]]) + T;
+    for (const V3 &b : dv)
       if (dot(a - b, a - b) < R2) return true;
-    }
   }
-  cell_triangles(g, c, V3{0, 0, 0}, tc);
+  cell_triangles(g, c, Xf(), tc);
   cell_triangles(g, d, T, td);
   const size_t nt = tc.bb.size() / 6, nd = td.bb.size() / 6;
   for (size_t i = 0; i < nt; ++i) {
@@ -452,12 +598,12 @@ static inline int img_code(int n0, int n1, int n2) { return 9 * (n0 + 1) + 3 * (
 
 // Closest-distance predicate (predicate AICA_DIL_CLOSEST), or the paper's vertex-to-vertex predicate
 // (AICA_DIL_VERTEX: some vertex of c and some vertex of d + T closer than R).
-static bool vertices_in_range(const Geometry &g, int32_t c, int32_t d, const V3 &T, double R) {
+static bool vertices_in_range(const Geometry &g, int32_t c, int32_t d, const Xf &T, double R) {
   const double R2 = R * R;
   for (int64_t i = g.cv_off[c]; i < g.cv_off[c + 1]; ++i) {
     const V3 a = mk(&g.pts[3 * (int64_t)g.cv[i]]);
     for (int64_t j = g.cv_off[d]; j < g.cv_off[d + 1]; ++j) {
-      const V3 b = mk(&g.pts[3 * (int64_t)g.cv[j]]) + T;
+      const V3 b = mapped(T, &g.pts[3 * (int64_t)g.cv[j]]);
       if (dot(a - b, a - b) < R2) return true;
     }
   }
@@ -467,6 +613,7 @@ static bool vertices_in_range(const Geometry &g, int32_t c, int32_t d, const V3 
 int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const std::vector<int32_t> &rank,
                      double R, int predicate, std::vector<CellPair> &out) {
   for (int k = 0; k < g.nper; ++k) {
+    if (g.gen[k].rot) continue;
     double L = std::sqrt(dot(mk(g.per[k]), mk(g.per[k])));
     if (!(R < 0.5 * L))
       return fail(AICA_E_RCUT, "rcut + guard must be below half of every periodic length (" + std::to_string(R) +
@@ -517,8 +664,33 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
       bcell[fill[b]++] = (int32_t)s;  // sorted id
     }
   }
-  int nimg = 1;
-  for (int k = 0; k < g.nper; ++k) nimg *= 3;
+  // images: the first powers (listed pairs); with a rotation also every other power (translations to
+  // +-2, rotations over their whole group), which must find no cell pair in range
+  struct Img {
+    Xf T, Tinv;
+    int n[3];
+  };
+  std::vector<Img> imgs, far;
+  {
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int k = 0; k < g.nper; ++k) {
+      lo[k] = g.gen[k].rot ? -((g.order[k] - 1) / 2) : -2;
+      hi[k] = g.gen[k].rot ? g.order[k] / 2 : 2;
+    }
+    for (int a = lo[0]; a <= hi[0]; ++a)
+      for (int b = lo[1]; b <= hi[1]; ++b)
+        for (int c = lo[2]; c <= hi[2]; ++c) {
+          Img im;
+          im.n[0] = a;
+          im.n[1] = b;
+          im.n[2] = c;
+          im.T = image_transform(g, a, b, c);
+          im.Tinv = im.T.inverse();
+          const bool first = std::abs(a) <= 1 && std::abs(b) <= 1 && std::abs(c) <= 1;
+          if (first) imgs.push_back(im);
+          else if (g.has_rot) far.push_back(im);
+        }
+  }
   const int nt = host_threads();
   std::vector<std::vector<CellPair>> per_thread(nt);
   std::vector<std::vector<CellPair>> per_chunk;
@@ -527,35 +699,37 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
   const int64_t chunk = 2048;
   const int64_t nchunks = (g.nc + chunk - 1) / chunk;
   per_chunk.resize(nchunks);
-  std::atomic<int64_t> next(0), n_cand(0), n_exact(0);
+  std::atomic<int64_t> next(0), n_cand(0), n_exact(0), n_far(0);
   std::vector<std::thread> th;
   for (int t = 0; t < nt; ++t)
     th.emplace_back([&]() {
       CellTris tc, td;
       std::vector<CellPair> local;
-      int64_t stat_cand = 0, stat_exact = 0;
+      int64_t stat_cand = 0, stat_exact = 0, stat_far = 0;
       for (;;) {
         int64_t ch = next.fetch_add(1);
         if (ch >= nchunks) break;
         local.clear();
         for (int64_t sc = ch * chunk; sc < std::min<int64_t>(g.nc, (ch + 1) * chunk); ++sc) {
           int32_t c = order[sc];
-          for (int im = 0; im < nimg; ++im) {
-            int n[3] = {0, 0, 0}, r = im;
-            for (int k = 0; k < g.nper; ++k) {
-              n[k] = r % 3 - 1;
-              r /= 3;
-            }
-            V3 T{0, 0, 0};
-            for (int k = 0; k < g.nper; ++k) T = T + mk(g.per[k]) * (double)n[k];
-            const int code = img_code(n[0], n[1], n[2]);
-            // centroid of d must lie within [lo_c - T - R - ext, hi_c - T + R + ext]
+          for (int pass = 0; pass < 2; ++pass)
+          for (const Img &im : pass == 0 ? imgs : far) {
+            const bool is_far = pass == 1;
+            const int *n = im.n;
+            const Xf &T = im.T;
+            const int code = is_far ? 0 : img_code(n[0], n[1], n[2]);
+            // d meets box_c grown by R after T, so its centroid lies within ext of T^-1 of that box
             int64_t b0[3], b1[3];
             bool empty = false;
+            double glo[3], ghi[3], qlo[3], qhi[3];
             for (int q = 0; q < 3; ++q) {
-              double Tq = q == 0 ? T.x : (q == 1 ? T.y : T.z);
-              double lo = g.lo[3 * (int64_t)c + q] - Tq - R - g.max_half_ext[q];
-              double hi = g.hi[3 * (int64_t)c + q] - Tq + R + g.max_half_ext[q];
+              glo[q] = g.lo[3 * (int64_t)c + q] - R;
+              ghi[q] = g.hi[3 * (int64_t)c + q] + R;
+            }
+            mapped_box(im.Tinv, glo, ghi, qlo, qhi);
+            for (int q = 0; q < 3; ++q) {
+              double lo = qlo[q] - g.max_half_ext[q];
+              double hi = qhi[q] + g.max_half_ext[q];
               if (hi < g.dom_lo[q] - bin || lo > g.dom_hi[q] + bin) empty = true;
               b0[q] = bin_of(lo, q);
               b1[q] = bin_of(hi, q);
@@ -567,6 +741,11 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
                   int64_t b = x + nb[0] * (y + nb[1] * z);
                   for (int64_t k = boff[b]; k < boff[b + 1]; ++k) {
                     const int32_t sd = bcell[k];
+                    if (is_far) {  // any cell pair through a farther image is an error
+                      if (quick_range(box[sc], box[sd], T, R) != 0 && cells_in_range(g, c, order[sd], T, R, tc, td))
+                        ++stat_far;
+                      continue;
+                    }
                     if (sd < sc || (sd == sc && code <= 13)) continue;  // canonical half
                     int q = quick_range(box[sc], box[sd], T, R);
                     ++stat_cand;
@@ -602,8 +781,12 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
       }
       n_cand += stat_cand;
       n_exact += stat_exact;
+      n_far += stat_far;
     });
   for (auto &x : th) x.join();
+  if (n_far.load() > 0)
+    return fail(AICA_E_RCUT, "rcut + guard reaches " + std::to_string(n_far.load()) +
+                                 " cell pairs through images beyond the first power of the periodic transforms");
   if (getenv("AICA_VERBOSE"))
     fprintf(stderr, "cell pairs: %lld candidates, %lld exact tests, %lld bins\n", (long long)n_cand.load(),
             (long long)n_exact.load(), (long long)nbins);

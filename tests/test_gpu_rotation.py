@@ -1,0 +1,199 @@
+"""GPU parity with referring transforms that rotate (Sec. 2.2.2): a sector of an annulus whose two
+sides are coupled by the rotation about z, periodic in z.
+
+Checks: forces, energy, virial, pair count and pair set against the FP64 oracle; the adjoint against
+the oracle; the binning against brute-force location; the GPU sector against the GPU whole annulus
+(rotated copies, z translation only); the torque about the axis and the axial force, which vanish
+for any rotationally periodic system.  Bars as for translations: FP64 1e-12, FP32 1e-5."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_cs_0702131_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_cs_0702131_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def eF(F, Fr):
+    rms = np.sqrt((Fr ** 2).sum(1).mean())
+    return np.sqrt(((F - Fr) ** 2).sum(1)).max() / rms
+
+
+def _near_cutoff(wl, rel):
+    """Canonical rows (a, b, n0, n1, 0) of the molecule pairs through a first image with a rotation
+    (n0 != 0) and |s - rc^2| < rel rc^2: the FP32 path rounds the rotated position (to about 1e-6 of
+    rc^2 in s), so these pairs may be decided either way.  Through a translation the decision is
+    exact on both sides (positions are multiples of 2^-15)."""
+    from scipy.spatial import cKDTree
+    w = wl.mesh.wedge
+    imgs, tags = W.wedge_images(wl.x, w["n_sectors"], w["Lz"])
+    allp = np.vstack(imgs)
+    n = wl.n
+    rc2 = wl.rcut ** 2
+    hits = cKDTree(allp).query_ball_point(wl.x, wl.rcut * np.sqrt(1 + rel))
+    rows = []
+    for a, lst in enumerate(hits):
+        for k in lst:
+            im, b = divmod(k, n)
+            if tags[im][0] == 0:
+                continue
+            s = ((wl.x[a] - allp[k]) ** 2).sum()
+            if abs(s - rc2) < rel * rc2:
+                rows.append((a, b, tags[im][0], tags[im][1], 0))
+    if not rows:
+        return np.zeros((0, 5), np.int64)
+    r = np.array(rows)
+    from oracle import oracle as O
+    return np.unique(O.canonical_pairs(r[:, 0], r[:, 1], r[:, 2:]), axis=0)
+
+
+def _pair_terms(wl, rows, oracle):
+    """Force (on a; -R^T f on b), energy and virial of the given canonical pairs."""
+    th, Lz = wl.mesh.wedge["theta"], wl.mesh.wedge["Lz"]
+    F = np.zeros((wl.n, 3))
+    U = Wv = 0.0
+    for a, b, n0, n1, _ in rows:
+        R = W.rot_z(n0 * th)
+        d = wl.x[a] - (R @ wl.x[b] + np.array([0.0, 0.0, n1 * Lz]))
+        s = d @ d
+        u, g = oracle.lj(s)
+        F[a] += g * d
+        F[b] -= R.T @ (g * d)
+        U += u
+        Wv += g * s
+    return F, U, Wv
+
+
+def _reconcile(wl, oracle, P, Pr, Fr, Ur, Wr, nr, amb):
+    """Pairs on which the two sides differ must all be near the cut-off (several answers are then
+    correct); the oracle's sums are moved to the GPU's decisions for those pairs."""
+    key = lambda M: {tuple(r) for r in M}
+    extra, missing = key(P) - key(Pr), key(Pr) - key(P)
+    assert (extra | missing) <= key(amb), (extra, missing)
+    Fr, Ur, Wr, nr = Fr.copy(), Ur, Wr, nr
+    for rows, sgn in ((extra, 1.0), (missing, -1.0)):
+        if rows:
+            dF, dU, dW = _pair_terms(wl, sorted(rows), oracle)
+            Fr += sgn * dF
+            Ur += sgn * dU
+            Wr += sgn * dW
+            nr += int(sgn) * len(rows)
+    return Fr, Ur, Wr, nr, len(extra) + len(missing)
+
+
+def _gpu_forces(A, wl, precision, dil=None):
+    import torch
+    d = dil or A.DIL(wl.mesh, wl.rcut)
+    x = torch.tensor(wl.x, dtype=torch.float64 if precision == "fp64" else torch.float32, device="cuda")
+    A.aica_bin(d, x)
+    F, uw, npairs = A.aica_forces(d, x, None, wl.eps, wl.sigma, precision=precision)
+    torch.cuda.synchronize()
+    return d, x, F.double().cpu().numpy(), uw.cpu().numpy(), int(npairs.cpu()[0])
+
+
+WEDGES = {
+    "small": dict(),
+    "r10-40": dict(r1=40.0, Lz=24.0, nr=25, nphi=24, nz=20),
+}
+
+
+@pytest.mark.parametrize("name", list(WEDGES))
+def test_wedge_forces_pairs_vs_oracle(A, oracle, name):
+    wl = W.wedge(**WEDGES[name])
+    _note(f"wedge {wl.name} n={wl.n} cells={wl.mesh.n_cells}")
+    amb = _near_cutoff(wl, 1e-5)
+    F0, U0, W0, n0 = oracle.forces(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.lattice, rot=wl.rotations)
+    Pr = oracle.pairs(wl.x, wl.rcut, wl.lattice, rot=wl.rotations)
+    assert (Pr[:, 2] != 0).sum() > 50  # pairs across the coupled sides
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        d, x, F, uw, npairs = _gpu_forces(A, wl, prec)
+        P = A.aica_pairs_export(d, x, precision=prec)
+        Fr, Ur, Wr, nr, ndiff = _reconcile(wl, oracle, P, Pr, F0, U0, W0, n0, amb)
+        e = eF(F, Fr)
+        _note(f"  {prec}: e_F {e:.2e} dU {abs(uw[0] - Ur) / abs(Ur):.2e} npairs {npairs} / {n0}, "
+              f"{ndiff} of {len(amb)} near-cut-off pairs decided the other way")
+        if prec == "fp64":
+            assert ndiff == 0
+        assert npairs == nr == len(P)
+        assert e < tol
+        assert abs(uw[0] - Ur) <= tol * abs(Ur) and abs(uw[1] - Wr) <= tol * abs(Wr)
+        d.close()
+
+
+def test_wedge_binning_vs_bruteforce(A, oracle):
+    import torch
+    wl = W.wedge()
+    d = A.DIL(wl.mesh, wl.rcut)
+    x = torch.tensor(wl.x, dtype=torch.float64, device="cuda")
+    A.aica_bin(d, x)
+    cell_of, _, count = A.aica_bin_export(d, wl.n)
+    ref = oracle.locate(wl.mesh, wl.x)
+    assert np.array_equal(cell_of, ref)
+    assert count.sum() == wl.n
+
+
+def test_wedge_torque_and_axial_force(A):
+    # invariants of rotational periodicity about z with a z translation (no oracle involved)
+    wl = W.wedge(r1=40.0, Lz=24.0, nr=25, nphi=24, nz=20)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        d, x, F, uw, npairs = _gpu_forces(A, wl, prec)
+        scale = np.abs(F).sum()
+        tz = (wl.x[:, 0] * F[:, 1] - wl.x[:, 1] * F[:, 0]).sum()
+        _note(f"  {prec}: torque_z {tz:.3e} F_z {F[:, 2].sum():.3e} (scale {scale:.3e})")
+        assert abs(tz) <= tol * scale * 40.0
+        assert abs(F[:, 2].sum()) <= tol * scale
+        d.close()
+
+
+def test_wedge_equals_whole_annulus_on_gpu(A):
+    # the sector (rotations) against the annulus of rotated copies (translations only), both on the GPU
+    wl = W.wedge()
+    K = wl.mesh.wedge["n_sectors"]
+    full, xf, _ = W.annulus_from_wedge(wl.mesh, wl.x)
+    fw = W.Workload("annulus", full, xf, np.zeros(len(xf), np.int32), wl.eps, wl.sigma, wl.rcut, None, None, ())
+    _, _, F, uw, npairs = _gpu_forces(A, wl, "fp64")
+    _, _, Ff, uwf, nf = _gpu_forces(A, fw, "fp64")
+    assert nf == K * npairs
+    assert abs(uwf[0] - K * uw[0]) <= 1e-11 * abs(uwf[0])
+    assert np.abs(Ff[:wl.n] - F).max() <= 1e-11 * np.sqrt((F ** 2).mean())
+
+
+def test_wedge_adjoint_vs_oracle(A, oracle):
+    import torch
+    wl = W.wedge(r1=30.0, Lz=12.0, nr=16, nphi=16, nz=10)
+    assert len(_near_cutoff(wl, 1e-5)) == 0  # one answer for every pair, so the gradients compare directly
+    G = W.qround(np.random.default_rng(61).standard_normal((wl.n, 3)))
+    gam = 0.2
+    rx, re, rs, rL = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.lattice, G, gam,
+                                    rot=wl.rotations)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        d = A.DIL(wl.mesh, wl.rcut)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        x = torch.tensor(wl.x, dtype=dt, device="cuda")
+        A.aica_bin(d, x)
+        gx, ge, gs = A.aica_forces_adjoint(d, x, torch.tensor(G, dtype=dt, device="cuda"), gam, None, wl.eps,
+                                           wl.sigma, precision=prec)
+        torch.cuda.synchronize()
+        gx = gx.double().cpu().numpy()
+        ex = np.abs(gx - rx).max() / np.sqrt((rx ** 2).mean())
+        ee = abs(ge.cpu().numpy()[0] - re[0]) / abs(re[0])
+        es = abs(gs.cpu().numpy()[0] - rs[0]) / abs(rs[0])
+        _note(f"  adjoint {prec}: dx {ex:.2e} deps {ee:.2e} dsig {es:.2e}")
+        assert ex < tol and ee < tol and es < tol
+        d.close()

@@ -146,3 +146,47 @@ def test_errors_mesh_and_rcut(A):
     with pytest.raises(A.AicaError) as e:
         A.DIL(skew, 1.0, 0.0)
     assert e.value.code == A.AICA_E_INVAL
+
+
+# ---------------------------------------------------------------- referring transforms with a rotation
+
+
+@pytest.mark.parametrize("seed,jitter", [(7, 0.2), (8, 0.0)])
+def test_dil_matches_bruteforce_wedge(A, oracle, seed, jitter):
+    # sector of an annulus: the sides are coupled by the rotation about z, z by a translation
+    m = W.wedge_mesh(10.0, 16.0, 12, 6.0, 4, 3, 3, jitter, np.random.default_rng(seed))
+    d = _dil_case(m, 2.5, 2.5e-6, A, oracle)
+    rot_pairs = d[d[:, 2] != 0]
+    assert len(rot_pairs) > 0 and set(np.unique(rot_pairs[:, 2])) == {-1, 1}
+
+
+def test_dil_wedge_far_images_rejected(A, oracle):
+    # near the axis the sector two rotations away is in range: the first powers would not suffice
+    narrow = W.wedge_mesh(1.5, 6.0, 8, 6.0, 3, 2, 3, 0.0, np.random.default_rng(1))
+    assert oracle.far_images(narrow, 2.5, 2.5e-6) > 0
+    with pytest.raises(A.AicaError) as e:
+        A.DIL(narrow, 2.5)
+    assert e.value.code == A.AICA_E_RCUT
+    ok = W.wedge_mesh(10.0, 16.0, 12, 6.0, 4, 3, 3, 0.0, np.random.default_rng(1))
+    assert oracle.far_images(ok, 2.5, 2.5e-6) == 0
+    A.DIL(ok, 2.5).close()
+
+
+def test_errors_referring_transforms(A):
+    m = W.wedge_mesh(10.0, 16.0, 12, 6.0, 4, 3, 3, 0.0, np.random.default_rng(1))
+    good = m.rotations.copy()
+    cases = [W.rot_z(1.0),                       # infinite order
+             W.rot_z(np.pi / 6) * 1.01,          # not orthonormal
+             np.diag([1.0, -1.0, 1.0]),          # a reflection
+             W.rot_z(np.pi)]                     # its own inverse
+    for r in cases:
+        m.rotations = np.stack([r, np.eye(3)])
+        with pytest.raises(A.AicaError) as e:
+            A.DIL(m, 2.5)
+        assert e.value.code == A.AICA_E_INVAL
+    # a rotation about z and a translation along x do not commute
+    m.rotations = good
+    m.periodic = np.array([[0.0, 0.0, 0.0], [6.0, 0.0, 0.0]])
+    with pytest.raises(A.AicaError) as e:
+        A.DIL(m, 2.5)
+    assert e.value.code == A.AICA_E_INVAL
