@@ -47,6 +47,8 @@ def workload(name):
         return W.config1()
     if name.startswith("channel@"):
         return W.config5(scale=float(name.split("@")[1]))
+    if name == "wedge":  # rotating referral: one of 12 sectors of an annulus, periodic in z
+        return W.wedge(seed=16, r0=100.0, r1=200.0, n_sectors=12, Lz=60.0, nr=83, nphi=90, nz=50, density=0.8)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -121,12 +123,13 @@ def cpu_baseline(wl, seconds_target, F32, F64, rng_seed=7):
     # calibrate on a few rows, then size the sample for the time target
     r0 = rng.choice(n, min(n, 4 * cores), replace=False)
     t = time.perf_counter()
-    O.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, r0)
+    O.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, r0, rot=wl.rotations)
     per_row = (time.perf_counter() - t) / len(r0)
     nrows = int(min(n, max(len(r0), seconds_target / max(per_row, 1e-9))))
     rows = rng.choice(n, nrows, replace=False)
     t = time.perf_counter()
-    Fr, Ur, Wr, cnt = O.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, rows)
+    Fr, Ur, Wr, cnt = O.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, rows,
+                                    rot=wl.rotations)
     t = time.perf_counter() - t
     t_full = t * n / nrows
     rms = np.sqrt((Fr ** 2).sum(1).mean())
