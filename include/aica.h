@@ -142,8 +142,9 @@ int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, v
  * summation order, no atomics on forces).  With AICA_FP32 the cut-off is still
  * decided exactly for positions that are multiples of 2^-15 (pairs within
  * 2^-20 rc^2 of rc^2 are decided in FP64), except for images with a rotation:
- * their referred positions are rounded to FP32 after the rotation, so a pair
- * within about 1e-6 rc of the cut-off may be decided either way.
+ * a rotated position is formed in FP64 and kept as an FP32 value plus its FP32
+ * remainder, so only a pair within about 1e-7 rc^2 of rc^2 may be decided
+ * either way (the adjoint uses the FP32 value alone).
  * Errors: AICA_E_INVAL, AICA_E_NOMEM, AICA_E_HIP. */
 int aica_forces(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
                 void *forces_dev, double *uw_dev, int64_t *npairs_dev, void *hip_stream);
