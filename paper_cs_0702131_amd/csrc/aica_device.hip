@@ -507,6 +507,7 @@ struct LJTab {
   float sig2[64], e24[64], e4[64];
   double sig2d[64], e24d[64], e4d[64];
   float rc2, band;
+  float rc2lo, rc2hi;  // rc^2 -+ band: an FP32 s below rc2lo is surely inside, at or above rc2hi surely outside
   double rc2d;
   int nsp;
 };
@@ -1103,6 +1104,8 @@ static int build_tab(const aica_dil *h, const aica_params *p, LJTab &t) {
   t.rc2d = p->rcut * p->rcut;
   t.rc2 = (float)t.rc2d;
   t.band = (float)(t.rc2d * std::ldexp(1.0, -20));
+  t.rc2lo = (float)(t.rc2d - (double)t.band);
+  t.rc2hi = (float)(t.rc2d + (double)t.band);
   t.nsp = p->n_species;
   return AICA_OK;
 }
