@@ -117,9 +117,11 @@ int aica_build_dil_ex(const aica_mesh *mesh, double rcut, double guard, int32_t 
  * molecule's cell (lowest cell index on a shared face), builds the CSR cell
  * occupancy and the cell-sorted order (ascending molecule id within a cell),
  * and the per-step work list.  Results stay in the handle.  Membership is
- * tracked from the previous call with the same n (Sec. 2.2): the previous
- * cell is tested first, then the cells across its faces, then a background
- * grid; the answer does not depend on the history.  Synchronises the stream
+ * tracked from the previous call with the same n (Sec. 2.2): a molecule still
+ * inside the ball kept from its last record test in its previous cell needs
+ * no test at all; otherwise the previous cell is tested first, then the cells
+ * across its faces, then a background grid.  The answer does not depend on
+ * the history (every route certifies the same cell).  Synchronises the stream
  * twice to read the unlocated and over-occupied counts.
  * Errors: AICA_E_INVAL (n < 0 or n >= 2^28 - 1, null, bad dtype, or a cell
  * holding more than 192 molecules), AICA_E_UNLOCATED (the count is in
@@ -187,6 +189,11 @@ typedef struct aica_info {
   int64_t n_cells, n_dil, n_groups, n_group_pairs, n_molecules, n_jslots;
   double mesh_volume, build_seconds, group_seconds;
   int64_t lane_steps;       /* reserved (-1) */
+  /* how the last aica_bin located its molecules: inside the ball kept from the
+   * molecule's last record test in the same cell (no geometry read), by the
+   * previous cell's FP32 record, or by the slow path (FP64 record, face
+   * neighbours, background grid) */
+  int64_t located_ball, located_record, located_search;
 } aica_info;
 int aica_dil_info(const aica_dil *dil, aica_info *info);
 

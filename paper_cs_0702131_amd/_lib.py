@@ -52,7 +52,8 @@ class aica_info(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_dil", C.c_int64), ("n_groups", C.c_int64),
                 ("n_group_pairs", C.c_int64), ("n_molecules", C.c_int64), ("n_jslots", C.c_int64),
                 ("mesh_volume", C.c_double), ("build_seconds", C.c_double), ("group_seconds", C.c_double),
-                ("lane_steps", C.c_int64)]
+                ("lane_steps", C.c_int64), ("located_ball", C.c_int64), ("located_record", C.c_int64),
+                ("located_search", C.c_int64)]
 
 
 _lib = None

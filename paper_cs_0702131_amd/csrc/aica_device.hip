@@ -114,8 +114,11 @@ struct aica_dil {
   int64_t jtotal = 0;
   DBuf d_cell_of, d_count, d_cell_start, d_fill, d_perm, d_g_start, d_mol_group, d_jcnt, d_slot_base, d_cell_sorted;
   DBuf d_scan_tmp, d_status, d_slow;
+  DBuf d_ref;                   // [n] float4 per caller molecule id: centre and radius of a ball that lies
+                                // inside the molecule's cell of the last binning (radius 0: none)
   DBuf d_perm_prev;     // the previous binning's permutation during aica_bin
   int64_t perm_n = -1;  // molecule count of the binning held in d_perm and d_cell_sorted (-1: none)
+  int64_t located[3] = {0, 0, 0};  // last binning: molecules located by their ball, by the FP32 record, slowly
   // force / adjoint workspace
   DBuf d_pos, d_own, d_jpart, d_gpart, d_gnp, d_gG, d_gpar;
   DBuf d_pairs, d_pcount;
@@ -261,6 +264,41 @@ __device__ bool surely_in_rec32(const double *p, const float4 *R) {
   return false;
 }
 
+// Radius of a ball about p that lies inside the cell of FP32 record R, for a p that the record shows
+// strictly inside: the cell's boundary is made of the face-fan triangles, and the distance from p to a
+// triangle is at least the distance to its plane, so the smallest plane distance bounds the distance to
+// the boundary from below.  FP32 rounding is covered by a margin of 1e-4 of the cell's size.  Returns the
+// ball as (centre rounded to FP32, radius reduced by that rounding); radius 0 when nothing is left.
+__device__ float4 inner_ball(const double *p, const float4 *R) {
+  const float4 h = R[0], h2 = R[1];
+  const int nf = (int)h.x;
+  const float pr[3] = {(float)(p[0] - (double)h.y), (float)(p[1] - (double)h.z), (float)(p[2] - (double)h.w)};
+  float dmin = 3.0e38f, size = 0.f;
+  int off = 0;
+  for (int k = 0; k < nf; ++k) {
+    const float4 f = R[2 + k];
+    const int len = (int)f.w;
+    const float e0 = f.x - h2.x, e1 = f.y - h2.y, e2 = f.z - h2.z;
+    size = fmaxf(size, sqrtf(e0 * e0 + e1 * e1 + e2 * e2));
+    const float4 *V = R + 2 + nf + off;
+    for (int j = 0; j < len; ++j) {
+      const float4 va = V[j], vb = V[j + 1 == len ? 0 : j + 1];
+      const float a0 = va.x - f.x, a1 = va.y - f.y, a2 = va.z - f.z;
+      const float b0 = vb.x - f.x, b1 = vb.y - f.y, b2 = vb.z - f.z;
+      const float n0 = a1 * b2 - a2 * b1, n1 = a2 * b0 - a0 * b2, n2 = a0 * b1 - a1 * b0;
+      const float nn = sqrtf(n0 * n0 + n1 * n1 + n2 * n2);
+      const float dd = fabsf(n0 * (pr[0] - f.x) + n1 * (pr[1] - f.y) + n2 * (pr[2] - f.z));
+      if (nn > 0.f) dmin = fminf(dmin, dd / nn);
+      else dmin = 0.f;
+    }
+    off += len;
+  }
+  const float pc[3] = {(float)p[0], (float)p[1], (float)p[2]};
+  const double s0 = p[0] - (double)pc[0], s1 = p[1] - (double)pc[1], s2 = p[2] - (double)pc[2];
+  const double r = (double)dmin * (1.0 - 1e-6) - 1e-4 * (double)size - sqrt(s0 * s0 + s1 * s1 + s2 * s2);
+  return make_float4(pc[0], pc[1], pc[2], r > 0 ? (float)r : 0.f);
+}
+
 // Locate each molecule: cell_of[i] = sorted index of the cell that contains x_i, in two kernels so that
 // the rare slow cases do not hold up whole waves.
 // k_locate_fast visits molecules in the order trav (the previous binning's sorted order, so that
@@ -274,23 +312,46 @@ __device__ bool surely_in_rec32(const double *p, const float4 *R) {
 // Both kernels index their state by t, the molecule's slot in the previous binning's sorted order
 // (trav[t] = its caller index, hint[t] = its previous cell; without a previous binning t is the
 // caller index and there is no hint), so that only the positions are read out of order.
+constexpr int kRouteSlots = 64;
+
 template <typename PT>
 __global__ void k_locate_fast(const PT *__restrict__ pos, int64_t n, const int32_t *__restrict__ trav,
                               const int32_t *__restrict__ hint, const float4 *__restrict__ rec32,
-                              int32_t *__restrict__ cell_t, int32_t *__restrict__ count,
-                              unsigned long long *__restrict__ nslow, int32_t *__restrict__ slow) {
+                              float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ count,
+                              unsigned long long *__restrict__ nslow, int32_t *__restrict__ slow,
+                              unsigned long long *__restrict__ routes) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int64_t i = trav ? trav[t] : t;
-  const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
-  const int32_t h0 = hint ? hint[t] : -1;
-  if (rec32 && h0 >= 0 && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) &&
-      surely_in_rec32(p, rec32 + (int64_t)kR32 * h0)) {
-    cell_t[t] = h0;
-    atomicAdd(&count[h0], 1);
-  } else {
-    slow[atomicAdd(nslow, 1ull)] = (int32_t)t;
+  int how = -1;  // 0: inside its ball, 1: the record test, 2: to the slow kernel
+  if (t < n) {
+    const int64_t i = trav ? trav[t] : t;
+    const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
+    const int32_t h0 = hint ? hint[t] : -1;
+    how = 2;
+    if (h0 >= 0 && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
+      // still inside the ball found inside this cell when it was last tested: no record needed
+      const float4 b = ref[i];
+      const double e0 = p[0] - (double)b.x, e1 = p[1] - (double)b.y, e2 = p[2] - (double)b.z;
+      if (b.w > 0.f && e0 * e0 + e1 * e1 + e2 * e2 < (double)b.w * (double)b.w) {
+        how = 0;
+      } else if (rec32) {
+        const float4 *R = rec32 + (int64_t)kR32 * h0;
+        if (surely_in_rec32(p, R)) {
+          how = 1;
+          ref[i] = inner_ball(p, R);
+        }
+      }
+    }
+    if (how < 2) {
+      cell_t[t] = h0;
+      atomicAdd(&count[h0], 1);
+    } else {
+      slow[atomicAdd(nslow, 1ull)] = (int32_t)t;
+    }
   }
+  // how many needed the record test (the rest: inside their ball or sent to the slow kernel), one atomic
+  // per wave that had any, spread over kRouteSlots counters so that the waves do not queue on one address
+  const unsigned long long m1 = __builtin_amdgcn_ballot_w64(how == 1);
+  if ((threadIdx.x & 63) == 0 && m1) atomicAdd(routes + blockIdx.x % kRouteSlots, (unsigned long long)__builtin_popcountll(m1));
 }
 
 template <typename PT>
@@ -301,7 +362,7 @@ __global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long lo
                               const int32_t *__restrict__ nbr, const double *__restrict__ bb,
                               const int64_t *__restrict__ gb_off, const int32_t *__restrict__ gb_cell, double glo0,
                               double glo1, double glo2, double gh, int64_t nb0, int64_t nb1, int64_t nb2,
-                              int32_t *__restrict__ cell_t, int32_t *__restrict__ count,
+                              float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ count,
                               unsigned long long *__restrict__ status) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= (int64_t)*nslow) return;
@@ -338,6 +399,7 @@ __global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long lo
     }
   }
   cell_t[t] = found;
+  ref[i] = make_float4(0.f, 0.f, 0.f, 0.f);  // no ball until the next record test in this cell
   if (found < 0)
     atomicAdd(status, 1ull);
   else
@@ -1007,11 +1069,16 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   if ((rc = h->d_jcnt.ensure(4 * std::max<int64_t>(nc, 1)))) return rc;
   if ((rc = h->d_slot_base.ensure(8 * (nc + 1)))) return rc;
   if ((rc = h->d_cell_sorted.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
-  if ((rc = h->d_status.ensure(64))) return rc;
+  if ((rc = h->d_status.ensure(8 * (8 + kRouteSlots)))) return rc;
   if ((rc = h->d_slow.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
+  if ((rc = h->d_ref.ensure(16 * std::max<int64_t>(n, 1)))) return rc;
+
   ProfScope ps(h, "bin", st);
   unsigned long long *status = h->d_status.as<unsigned long long>();
-  hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, status, (int64_t)8, 0ull);
+  // status: [0] unlocated, [1] over-full cells, [2] slow-kernel molecules, [8 ..) record-test counters
+  hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(8 + kRouteSlots), 0, st, status,
+                     (int64_t)(8 + kRouteSlots), 0ull);
+  unsigned long long *routes = status + 8;
   hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(), nc, 0);
   hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_fill.as<int32_t>(), nc, 0);
   // the previous binning of the same n (if any) gives the traversal order and the hints: its
@@ -1028,12 +1095,13 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
     unsigned long long *nslow = status + 2;
 #define AICA_LOCATE(PT)                                                                                            \
   hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const PT *)pos_dev, n, trav, hint, \
-                     r32, h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), nslow, slow);                       \
+                     r32, h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), nslow,     \
+                     slow, routes);                                                                                 \
   hipLaunchKernelGGL((k_locate_slow<PT>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const PT *)pos_dev, nslow, slow, \
                      trav, hint, h->d_rec_off.as<int64_t>(), h->d_rec.as<double>(), h->d_nbr_off.as<int64_t>(),   \
                      h->d_nbr.as<int32_t>(), h->d_bb.as<double>(), h->d_gb_off.as<int64_t>(),                       \
                      h->d_gb_cell.as<int32_t>(), h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1],      \
-                     h->gnb[2], h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status)
+                     h->gnb[2], h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status)
     if (pos_dtype == AICA_FP64) {
       AICA_LOCATE(double);
     } else {
@@ -1062,10 +1130,15 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   HIPCHK(hipGetLastError());
   if ((rc = scan_exclusive<int64_t>(h, h->d_jcnt.as<int32_t>(), nc, h->d_slot_base.as<int64_t>(), st))) return rc;
   int64_t jt = 0;
-  unsigned long long over = 0;
+  unsigned long long stat[8 + kRouteSlots];
   HIPCHK(hipMemcpyAsync(&jt, h->d_slot_base.as<int64_t>() + nc, 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(&over, status + 1, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(stat, status, sizeof stat, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  const unsigned long long over = stat[1];
+  h->located[1] = 0;
+  for (int k = 0; k < kRouteSlots; ++k) h->located[1] += (int64_t)stat[8 + k];
+  h->located[2] = (int64_t)stat[2];
+  h->located[0] = n - h->located[1] - h->located[2];
   if (over > 0)
     return fail(AICA_E_INVAL, std::to_string(over) + " cell(s) hold more than " + std::to_string(kLCap) +
                                   " molecules; refine the mesh");
@@ -1380,6 +1453,9 @@ int aica_dil_info(const aica_dil *h, aica_info *info) {
   info->build_seconds = h->build_seconds;
   info->group_seconds = h->group_seconds;
   info->lane_steps = -1;
+  info->located_ball = h->located[0];
+  info->located_record = h->located[1];
+  info->located_search = h->located[2];
   return AICA_OK;
 }
 

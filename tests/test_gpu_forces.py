@@ -307,3 +307,34 @@ def test_binning_ties_on_faces_edges_vertices(A, oracle):
         A.aica_bin(d, t)
         cell_of, order, count = A.aica_bin_export(d, len(x))
         assert np.array_equal(cell_of, oracle.locate(mesh, x)), step
+
+
+def test_binning_balls_and_routes(A, oracle):
+    """Tracking (the paper's membership kept from step to step): the first binning searches, the second
+    tests every molecule against its previous cell's record and keeps a ball inside that cell, the third
+    (same positions) needs no geometry at all; small moves then mix the routes.  Every binning equals
+    brute-force location, and the routes add up to n."""
+    import torch
+    wl = W.small_random(n_mesh=(5, 4, 5), L=(10.0, 8.0, 10.0), N=500, seed=31, mesh_jitter=0.25)
+    d = A.DIL(wl.mesh, wl.rcut)
+    x = wl.x.copy()
+    rng = np.random.default_rng(32)
+    routes = []
+    for step in range(6):
+        if step >= 3:  # moves of up to 0.15 per axis, wrapped into the periodic box
+            x = W.qround(W.wrap(x + rng.uniform(-0.15, 0.15, size=x.shape), wl.box_lo, wl.box_hi,
+                                wl.periodic_axes))
+            x = np.minimum(x, wl.box_hi - W.Q)
+        t = torch.tensor(x, device="cuda")
+        A.aica_bin(d, t)
+        cell_of, _, _ = A.aica_bin_export(d, len(x))
+        assert np.array_equal(cell_of, oracle.locate(wl.mesh, x)), step
+        inf = d.info()
+        r = (inf["located_ball"], inf["located_record"], inf["located_search"])
+        routes.append(r)
+        assert sum(r) == len(x), (step, r)
+    _note(f"routes (ball, record, search) per binning: {routes}")
+    assert routes[0] == (0, 0, len(x))
+    assert routes[1][0] == 0 and routes[1][1] >= 0.95 * len(x)
+    assert routes[2][0] >= 0.95 * len(x)
+    assert routes[5][0] > 0 and routes[5][1] + routes[5][2] > 0

@@ -35,8 +35,12 @@ def run_nve(A, d, wl, precision, steps=100, dt=0.005):
     R = wl.extra["post_r"] + 1e-4  # reflect just outside the deleted cells (q-rounding stays outside)
     L = [float(b) for b in wl.box_hi]
 
+    routes = []
+
     def forces(x):
         A.aica_bin(d, x)
+        inf = d.info()
+        routes.append((inf["located_ball"], inf["located_record"], inf["located_search"]))
         F, uw, npairs = A.aica_forces(d, x, None, wl.eps, wl.sigma, precision=precision)
         return F.double(), float(uw[0].item()), int(npairs.item())
 
@@ -68,6 +72,9 @@ def run_nve(A, d, wl, precision, steps=100, dt=0.005):
         F, U, npairs = forces(x)
         v = v + 0.5 * dt * F
         E.append(0.5 * float((v * v).sum().item()) + U - npairs * U_RC)
+    r = np.array(routes[2:], dtype=np.float64)  # after the first two binnings (no history, then no balls)
+    print(f"{precision}: molecules per binning located by ball / record / search: "
+          f"{r[:, 0].mean():.0f} / {r[:, 1].mean():.0f} / {r[:, 2].mean():.0f}", flush=True)
     return x.cpu().numpy(), np.array(E)
 
 
