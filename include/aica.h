@@ -122,7 +122,7 @@ int aica_build_dil_ex(const aica_mesh *mesh, double rcut, double guard, int32_t 
  * no test at all; otherwise the previous cell is tested first, then the cells
  * across its faces, then a background grid.  The answer does not depend on
  * the history (every route certifies the same cell).  Synchronises the stream
- * twice to read the unlocated and over-occupied counts.
+ * once, to read the unlocated, over-occupied and reaction-slot counts.
  * Errors: AICA_E_INVAL (n < 0 or n >= 2^28 - 1, null, bad dtype, or a cell
  * holding more than 192 molecules), AICA_E_UNLOCATED (the count is in
  * aica_last_error), AICA_E_NOMEM (more than 2^31 reaction records), AICA_E_HIP. */

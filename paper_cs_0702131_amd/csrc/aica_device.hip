@@ -112,7 +112,7 @@ struct aica_dil {
   const void *bin_pos = nullptr;
   int32_t bin_dtype = 0;
   int64_t jtotal = 0;
-  DBuf d_cell_of, d_count, d_cell_start, d_fill, d_perm, d_g_start, d_mol_group, d_jcnt, d_slot_base, d_cell_sorted;
+  DBuf d_cell_of, d_count, d_cell_start, d_rank, d_perm, d_g_start, d_mol_group, d_jcnt, d_slot_base, d_cell_sorted;
   DBuf d_scan_tmp, d_status, d_slow;
   DBuf d_ref;                   // [n] float4 per caller molecule id: centre and radius of a ball that lies
                                 // inside the molecule's cell of the last binning (radius 0: none)
@@ -317,9 +317,9 @@ constexpr int kRouteSlots = 64;
 template <typename PT>
 __global__ void k_locate_fast(const PT *__restrict__ pos, int64_t n, const int32_t *__restrict__ trav,
                               const int32_t *__restrict__ hint, const float4 *__restrict__ rec32,
-                              float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ count,
-                              unsigned long long *__restrict__ nslow, int32_t *__restrict__ slow,
-                              unsigned long long *__restrict__ routes) {
+                              float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ rank_t,
+                              int32_t *__restrict__ count, unsigned long long *__restrict__ nslow,
+                              int32_t *__restrict__ slow, unsigned long long *__restrict__ routes) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int how = -1;  // 0: inside its ball, 1: the record test, 2: to the slow kernel
   if (t < n) {
@@ -343,7 +343,7 @@ __global__ void k_locate_fast(const PT *__restrict__ pos, int64_t n, const int32
     }
     if (how < 2) {
       cell_t[t] = h0;
-      atomicAdd(&count[h0], 1);
+      rank_t[t] = atomicAdd(&count[h0], 1);
     } else {
       slow[atomicAdd(nslow, 1ull)] = (int32_t)t;
     }
@@ -355,18 +355,14 @@ __global__ void k_locate_fast(const PT *__restrict__ pos, int64_t n, const int32
 }
 
 template <typename PT>
-__global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long long *__restrict__ nslow,
-                              const int32_t *__restrict__ slow, const int32_t *__restrict__ trav,
-                              const int32_t *__restrict__ hint, const int64_t *__restrict__ rec_off,
-                              const double *__restrict__ rec, const int64_t *__restrict__ nbr_off,
-                              const int32_t *__restrict__ nbr, const double *__restrict__ bb,
-                              const int64_t *__restrict__ gb_off, const int32_t *__restrict__ gb_cell, double glo0,
-                              double glo1, double glo2, double gh, int64_t nb0, int64_t nb1, int64_t nb2,
-                              float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ count,
-                              unsigned long long *__restrict__ status) {
-  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= (int64_t)*nslow) return;
-  const int64_t t = slow[u];
+__device__ void locate_slow_one(const PT *__restrict__ pos, const int64_t t, const int32_t *__restrict__ trav,
+                                const int32_t *__restrict__ hint, const int64_t *__restrict__ rec_off,
+                                const double *__restrict__ rec, const int64_t *__restrict__ nbr_off,
+                                const int32_t *__restrict__ nbr, const double *__restrict__ bb,
+                                const int64_t *__restrict__ gb_off, const int32_t *__restrict__ gb_cell, double glo0,
+                                double glo1, double glo2, double gh, int64_t nb0, int64_t nb1, int64_t nb2,
+                                float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ rank_t,
+                                int32_t *__restrict__ count, unsigned long long *__restrict__ status) {
   const int64_t i = trav ? trav[t] : t;
   const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
   const bool finite = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
@@ -403,8 +399,26 @@ __global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long lo
   if (found < 0)
     atomicAdd(status, 1ull);
   else
-    atomicAdd(&count[found], 1);
+    rank_t[t] = atomicAdd(&count[found], 1);
 }
+
+template <typename PT>
+__global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long long *__restrict__ nslow,
+                              const int32_t *__restrict__ slow, const int32_t *__restrict__ trav,
+                              const int32_t *__restrict__ hint, const int64_t *__restrict__ rec_off,
+                              const double *__restrict__ rec, const int64_t *__restrict__ nbr_off,
+                              const int32_t *__restrict__ nbr, const double *__restrict__ bb,
+                              const int64_t *__restrict__ gb_off, const int32_t *__restrict__ gb_cell, double glo0,
+                              double glo1, double glo2, double gh, int64_t nb0, int64_t nb1, int64_t nb2,
+                              float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ rank_t,
+                              int32_t *__restrict__ count, unsigned long long *__restrict__ status) {
+  // a fixed grid strides over the list, whose length is only known on the device
+  const int64_t ns = (int64_t)*nslow;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < ns; u += (int64_t)gridDim.x * blockDim.x)
+    locate_slow_one<PT>(pos, slow[u], trav, hint, rec_off, rec, nbr_off, nbr, bb, gb_off, gb_cell, glo0, glo1, glo2,
+                        gh, nb0, nb1, nb2, ref, cell_t, rank_t, count, status);
+}
+
 
 // ---- exclusive scan of int32 counts into OutT offsets (out[n] = total)
 
@@ -479,13 +493,14 @@ __global__ void k_scan_add(OutT *out, int64_t n, const OutT *tile_sum) {
   if (i < n) out[i] += tile_sum[i / kScanTile];
 }
 
+// rank_t[t]: the place the locate kernels' count took for the molecule inside its cell (any order; the
+// cells are sorted by molecule id next).
 __global__ void k_scatter(const int32_t *cell_t, const int32_t *trav, int64_t n, const int32_t *cell_start,
-                          int32_t *fill, int32_t *perm) {
+                          const int32_t *rank_t, int32_t *perm) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int32_t c = cell_t[t];
-  const int32_t slot = cell_start[c] + atomicAdd(&fill[c], 1);
-  perm[slot] = trav ? trav[t] : (int32_t)t;
+  if (c >= 0) perm[cell_start[c] + rank_t[t]] = trav ? trav[t] : (int32_t)t;  // c < 0: unlocated (an error)
 }
 
 // Ascending molecule id inside every cell (the scatter's atomics leave an arbitrary order).
@@ -1062,7 +1077,7 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   if ((rc = h->d_cell_of.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
   if ((rc = h->d_count.ensure(4 * nc))) return rc;
   if ((rc = h->d_cell_start.ensure(4 * (nc + 1)))) return rc;
-  if ((rc = h->d_fill.ensure(4 * nc))) return rc;
+  if ((rc = h->d_rank.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
   if ((rc = h->d_perm.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
   if ((rc = h->d_g_start.ensure(4 * (ng + 1)))) return rc;
   if ((rc = h->d_mol_group.ensure(4 * std::max<int64_t>(n, 1)))) return rc;
@@ -1080,7 +1095,6 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
                      (int64_t)(8 + kRouteSlots), 0ull);
   unsigned long long *routes = status + 8;
   hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(), nc, 0);
-  hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_fill.as<int32_t>(), nc, 0);
   // the previous binning of the same n (if any) gives the traversal order and the hints: its
   // permutation moves to d_perm_prev, and d_cell_sorted still holds its cells until rebuilt below
   const bool prev = h->perm_n == n && n > 0;
@@ -1095,13 +1109,14 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
     unsigned long long *nslow = status + 2;
 #define AICA_LOCATE(PT)                                                                                            \
   hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const PT *)pos_dev, n, trav, hint, \
-                     r32, h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), nslow,     \
-                     slow, routes);                                                                                 \
-  hipLaunchKernelGGL((k_locate_slow<PT>), dim3(grid1d(n, 128)), dim3(128), 0, st, (const PT *)pos_dev, nslow, slow, \
+                     r32, h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_rank.as<int32_t>(),             \
+                     h->d_count.as<int32_t>(), nslow, slow, routes);                                                \
+  hipLaunchKernelGGL((k_locate_slow<PT>), dim3(std::min<int64_t>(grid1d(n, 128), 2048)), dim3(128), 0, st, (const PT *)pos_dev, nslow, slow, \
                      trav, hint, h->d_rec_off.as<int64_t>(), h->d_rec.as<double>(), h->d_nbr_off.as<int64_t>(),   \
                      h->d_nbr.as<int32_t>(), h->d_bb.as<double>(), h->d_gb_off.as<int64_t>(),                       \
                      h->d_gb_cell.as<int32_t>(), h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1],      \
-                     h->gnb[2], h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_count.as<int32_t>(), status)
+                     h->gnb[2], h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_rank.as<int32_t>(),       \
+                     h->d_count.as<int32_t>(), status)
     if (pos_dtype == AICA_FP64) {
       AICA_LOCATE(double);
     } else {
@@ -1110,15 +1125,13 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
 #undef AICA_LOCATE
     HIPCHK(hipGetLastError());
   }
-  unsigned long long unl = 0;
-  HIPCHK(hipMemcpyAsync(&unl, status, 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (unl > 0) return fail(AICA_E_UNLOCATED, std::to_string(unl) + " molecule(s) lie in no mesh cell");
+  // the unlocated count is read with the other counts below (one synchronisation per binning); an
+  // unlocated molecule is left out of the occupancy and of the permutation
   hipLaunchKernelGGL(k_max_count, dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(), nc, status);
   if ((rc = scan_exclusive<int32_t>(h, h->d_count.as<int32_t>(), nc, h->d_cell_start.as<int32_t>(), st))) return rc;
   if (n > 0)
     hipLaunchKernelGGL(k_scatter, dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_cell_of.as<int32_t>(), trav, n,
-                       h->d_cell_start.as<int32_t>(), h->d_fill.as<int32_t>(), h->d_perm.as<int32_t>());
+                       h->d_cell_start.as<int32_t>(), h->d_rank.as<int32_t>(), h->d_perm.as<int32_t>());
   hipLaunchKernelGGL(k_sort_cells, dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_cell_start.as<int32_t>(), nc,
                      h->d_perm.as<int32_t>());
   hipLaunchKernelGGL(k_group_ranges, dim3(grid1d(ng + 1, 256)), dim3(256), 0, st, h->d_cell_start.as<int32_t>(),
@@ -1134,7 +1147,8 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   HIPCHK(hipMemcpyAsync(&jt, h->d_slot_base.as<int64_t>() + nc, 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(stat, status, sizeof stat, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  const unsigned long long over = stat[1];
+  const unsigned long long unl = stat[0], over = stat[1];
+  if (unl > 0) return fail(AICA_E_UNLOCATED, std::to_string(unl) + " molecule(s) lie in no mesh cell");
   h->located[1] = 0;
   for (int k = 0; k < kRouteSlots; ++k) h->located[1] += (int64_t)stat[8 + k];
   h->located[2] = (int64_t)stat[2];
