@@ -66,10 +66,21 @@ typedef struct {
   double R[9];
   double y[3];
   int n[3];
+  int rot; /* 0: R is the identity (a plain translation by y) */
 } oc_xf;
 
 static void oc_xf_apply(const oc_xf *t, const double *x, double *o) {
+  if (!t->rot) {
+    for (int q = 0; q < 3; ++q) o[q] = x[q] + t->y[q];
+    return;
+  }
   for (int q = 0; q < 3; ++q) o[q] = t->R[3 * q] * x[0] + t->R[3 * q + 1] * x[1] + t->R[3 * q + 2] * x[2] + t->y[q];
+}
+
+static void oc_xf_set_rot(oc_xf *t) {
+  t->rot = 0;
+  for (int i = 0; i < 9; ++i)
+    if (t->R[i] != ((i % 4 == 0) ? 1.0 : 0.0)) t->rot = 1;
 }
 
 /* rotation part only (how vectors such as forces and G transform) */
@@ -86,6 +97,7 @@ static void oc_xf_compose(const oc_xf *a, const oc_xf *b, oc_xf *o) {
     r.y[i] = a->R[3 * i] * b->y[0] + a->R[3 * i + 1] * b->y[1] + a->R[3 * i + 2] * b->y[2] + a->y[i];
   }
   for (int k = 0; k < 3; ++k) r.n[k] = 0;
+  oc_xf_set_rot(&r);
   *o = r;
 }
 
@@ -95,6 +107,7 @@ static void oc_xf_identity(oc_xf *t) {
     t->y[q] = 0.0;
     t->n[q] = 0;
   }
+  t->rot = 0;
 }
 
 static int oc_xf_is_identity(const oc_xf *t, double scale) {
@@ -111,12 +124,14 @@ static void oc_generator(const double *lat, const double *rot, int k, int invers
   if (rot)
     for (int i = 0; i < 9; ++i) t->R[i] = rot[9 * k + i];
   for (int q = 0; q < 3; ++q) t->y[q] = lat[3 * k + q];
+  oc_xf_set_rot(t);
   if (inverse) { /* x = R^T (x' - y) */
     oc_xf v;
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) v.R[3 * i + j] = t->R[3 * j + i];
     for (int i = 0; i < 3; ++i) v.y[i] = -(v.R[3 * i] * t->y[0] + v.R[3 * i + 1] * t->y[1] + v.R[3 * i + 2] * t->y[2]);
     for (int q = 0; q < 3; ++q) v.n[q] = 0;
+    oc_xf_set_rot(&v);
     *t = v;
   }
 }
@@ -796,6 +811,7 @@ double oc_cell_distance(int64_t n_points, const double *points, int64_t n_faces,
   for (int q = 0; q < 3; ++q) t.y[q] = T[q];
   if (Rm)
     for (int i = 0; i < 9; ++i) t.R[i] = Rm[i];
+  oc_xf_set_rot(&t);
   oc_cell Dm;
   oc_cell_mapped(&cells[d], &t, &Dm);
   double best = 1e300;
