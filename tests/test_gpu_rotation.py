@@ -197,3 +197,72 @@ def test_wedge_adjoint_vs_oracle(A, oracle):
         _note(f"  adjoint {prec}: dx {ex:.2e} deps {ee:.2e} dsig {es:.2e}")
         assert ex < tol and ee < tol and es < tol
         d.close()
+
+
+def test_wedge_nve_angular_momentum(A):
+    """Velocity Verlet in the sector (FP64), molecules crossing the coupled sides (wrapped by the
+    sector rotation, position and velocity) and z, reflected at the walls.  Every pair force is central
+    and the referred copies are rotated consistently, so the angular momentum about the axis and the
+    axial momentum are conserved to rounding; the shifted energy stays close to its start."""
+    import math
+    import torch
+    wl = W.wedge(r1=30.0, Lz=12.0, nr=16, nphi=16, nz=10)
+    w = wl.mesh.wedge
+    th, Lz = w["theta"], w["Lz"]
+    rmin = w["r0"] + 1e-3
+    rmax = w["r1"] * math.cos(0.5 * th / w["nphi"]) - 1e-3  # inside the chords of the outer wall
+    n = wl.n
+    d = A.DIL(wl.mesh, wl.rcut)
+    dev = "cuda"
+    x = torch.tensor(wl.x, dtype=torch.float64, device=dev)
+    g = torch.Generator(device="cpu").manual_seed(71)
+    v = (0.7 * torch.randn(n, 3, generator=g, dtype=torch.float64)).to(dev)
+    v -= v.mean(0)
+    R1 = torch.tensor(W.rot_z(th), dtype=torch.float64, device=dev)
+    U_RC = 4.0 * (2.5 ** -12 - 2.5 ** -6)
+
+    def forces(x):
+        A.aica_bin(d, x)
+        F, uw, npairs = A.aica_forces(d, x, None, wl.eps, wl.sigma, precision="fp64")
+        return F, float(uw[0].item()), int(npairs.item())
+
+    def invariants(x, v, U, npairs):
+        Lzv = float((x[:, 0] * v[:, 1] - x[:, 1] * v[:, 0]).sum().item())
+        scale = float((x[:, 0] * v[:, 1] - x[:, 1] * v[:, 0]).abs().sum().item())
+        E = 0.5 * float((v * v).sum().item()) + U - npairs * U_RC
+        return Lzv, scale, float(v[:, 2].sum().item()), E
+
+    F, U, npairs = forces(x)
+    L0, scale, P0, E0 = invariants(x, v, U, npairs)
+    dt, crossings = 0.002, 0
+    Emax = 0.0
+    for step in range(300):
+        v = v + 0.5 * dt * F
+        x = x + dt * v
+        # walls: reflect the radial component
+        r = torch.sqrt(x[:, 0] ** 2 + x[:, 1] ** 2)
+        for lim, out in ((rmin, r < rmin), (rmax, r > rmax)):
+            if bool(out.any()):
+                nx, ny = x[out, 0] / r[out], x[out, 1] / r[out]
+                rn = 2 * lim - r[out]
+                x[out, 0], x[out, 1] = nx * rn, ny * rn
+                vn = v[out, 0] * nx + v[out, 1] * ny
+                v[out, 0] -= 2 * vn * nx
+                v[out, 1] -= 2 * vn * ny
+        # coupled sides: a molecule leaving through one re-enters through the other, turned by the rotation
+        phi = torch.atan2(x[:, 1], x[:, 0])
+        lo, hi = phi < 0, phi >= th
+        crossings += int(lo.sum().item() + hi.sum().item())
+        x[lo], v[lo] = x[lo] @ R1.T, v[lo] @ R1.T
+        x[hi], v[hi] = x[hi] @ R1, v[hi] @ R1
+        x[:, 2] = torch.remainder(x[:, 2], Lz)
+        F, U, npairs = forces(x)
+        v = v + 0.5 * dt * F
+        L, _, P, E = invariants(x, v, U, npairs)
+        Emax = max(Emax, abs(E - E0) / n)
+    _note(f"  NVE wedge: {crossings} side crossings; |dLz|/sum|Lz_i| {abs(L - L0) / scale:.2e}, "
+          f"|dPz| {abs(P - P0):.2e}, max |E-E0|/N {Emax:.2e}")
+    assert crossings > 10
+    assert abs(L - L0) <= 1e-11 * scale
+    assert abs(P - P0) <= 1e-11 * float(v.abs().sum().item())
+    assert Emax < 1e-2
