@@ -1,0 +1,71 @@
+"""The benchmark's workload at full size (6,683,992 molecules, 4,312,968 cells of the graded jittered
+channel), in the launch configuration the benchmark times: FP32 and FP64 forces on sampled rows
+against the oracle (each row summed over every molecule and image), equal pair counts in both
+precisions, and the adjoint's invariants (translation invariance of L, eps-homogeneity)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_cs_0702131_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_cs_0702131_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_channel_full_size(A, oracle):
+    import torch
+    t0 = time.time()
+    wl = W.config5()
+    _note(f"channel: {wl.n} molecules, {wl.mesh.n_cells} cells ({time.time() - t0:.1f}s); building lists")
+    d = A.DIL(wl.mesh, wl.rcut)
+    _note(f"lists built ({time.time() - t0:.1f}s)")
+    rows = np.random.default_rng(51).choice(wl.n, 256, replace=False)
+    Fr, Ur, Wr, cnt = oracle.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, rows)
+    rms = np.sqrt((Fr ** 2).sum(1).mean())
+    _note(f"oracle rows done ({time.time() - t0:.1f}s)")
+    npairs = {}
+    for prec, tol, dt in (("fp32", 1e-5, torch.float32), ("fp64", 1e-12, torch.float64)):
+        x = torch.tensor(wl.x, dtype=dt, device="cuda")
+        A.aica_bin(d, x)
+        F, uw, n = A.aica_forces(d, x, None, wl.eps, wl.sigma, precision=prec)
+        torch.cuda.synchronize()
+        F = F.double().cpu().numpy()
+        npairs[prec] = int(n.cpu()[0])
+        err = np.sqrt(((F[rows] - Fr) ** 2).sum(1)).max() / rms
+        _note(f"  {prec}: sampled e_F {err:.3e}, npairs {npairs[prec]}")
+        assert err < tol
+        # per-row pair counts of the oracle are half-sums over both members; their total is not the
+        # global count, so the global count is compared between the precisions below
+    assert npairs["fp32"] == npairs["fp64"]
+    # adjoint invariants at full size, FP32
+    G = W.qround(np.random.default_rng(52).standard_normal((wl.n, 3)))
+    gam = 0.1
+    x = torch.tensor(wl.x, dtype=torch.float32, device="cuda")
+    A.aica_bin(d, x)
+    Gt = torch.tensor(G, dtype=torch.float32, device="cuda")
+    gx, ge, gs = A.aica_forces_adjoint(d, x, Gt, gam, None, wl.eps, wl.sigma, precision="fp32")
+    F, uw, _ = A.aica_forces(d, x, None, wl.eps, wl.sigma, precision="fp32")
+    torch.cuda.synchronize()
+    gx = gx.double().cpu().numpy()
+    L = float((G * F.double().cpu().numpy()).sum() + gam * uw[0].item())
+    tinv = np.abs(gx.sum(0)).max() / np.abs(gx).sum(0).max()
+    homog = abs(float(wl.eps[0] * ge.cpu().numpy()[0]) - L) / abs(L)
+    _note(f"  adjoint fp32: |sum dL/dx| / sum |dL/dx| {tinv:.3e}, eps-homogeneity {homog:.3e} ({time.time() - t0:.1f}s)")
+    assert tinv < 1e-5
+    assert homog < 1e-5
