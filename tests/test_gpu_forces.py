@@ -338,3 +338,42 @@ def test_binning_balls_and_routes(A, oracle):
     assert routes[1][0] == 0 and routes[1][1] >= 0.95 * len(x)
     assert routes[2][0] >= 0.95 * len(x)
     assert routes[5][0] > 0 and routes[5][1] + routes[5][2] > 0
+
+
+def test_cells_at_the_occupancy_limit(A, oracle):
+    """Eight cells of 180 molecules each (the limit is 192): a neighbour cell never fits beside the
+    j carried over from the previous segment, so every segment boundary takes the path that first
+    evaluates the carried j on their own; groups hold one cell, i.e. three passes of up to 64."""
+    import torch
+    L, per = 12.0, 180
+    sites = []
+    for ci in range(2):
+        for cj in range(2):
+            for ck in range(2):
+                a, b, c = np.meshgrid(np.arange(6), np.arange(6), np.arange(5), indexing="ij")
+                s = np.stack([ci * 6 + 0.5 + a.ravel() * 1.0, cj * 6 + 0.5 + b.ravel() * 1.0,
+                              ck * 6 + 0.6 + c.ravel() * 1.2], axis=1)
+                sites.append(s)
+    x = np.vstack(sites)
+    x = W.qround(x + np.random.default_rng(61).uniform(-0.1, 0.1, size=x.shape))
+    nodes = W.uniform_nodes(L, 2)
+    mesh = W.hex_mesh(nodes, nodes, nodes, periodic_axes=(0, 1, 2), shuffle_seed=62)
+    n = len(x)
+    wl = W.Workload("limit", mesh, x, np.zeros(n, np.int32), np.array([1.0]), np.array([1.0]), 2.5,
+                    np.zeros(3), np.full(3, L), (0, 1, 2))
+    d, _, _, _, _ = run_gpu(A, wl, "fp64")
+    _, _, count = A.aica_bin_export(d, n)
+    assert count.max() == per and count.min() == per
+    check_case(A, oracle, wl, "fp64", 1e-12, 1e-12)
+    # U/N is only -0.07 here (close repulsive and attractive pairs nearly cancel), so the FP32 pair
+    # energies' relative error of ~1e-7 shows up amplified in U: the bar is 2e-5 of |U| for this case
+    check_case(A, oracle, wl, "fp32", 1e-5, 2e-5)
+    G = W.qround(np.random.default_rng(63).standard_normal((n, 3)))
+    rx, _, _, _ = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, 0.1)
+    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-5)):
+        xt = torch.tensor(wl.x, dtype=dt, device="cuda")
+        A.aica_bin(d, xt)
+        gx, _, _ = A.aica_forces_adjoint(d, xt, torch.tensor(G, dtype=dt, device="cuda"), 0.1, None, wl.eps,
+                                         wl.sigma, precision=prec)
+        gx = gx.double().cpu().numpy()
+        assert np.abs(gx - rx).max() / np.sqrt((rx ** 2).mean()) < tol, prec
