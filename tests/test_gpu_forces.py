@@ -341,18 +341,19 @@ def test_binning_balls_and_routes(A, oracle):
 
 
 def test_cells_at_the_occupancy_limit(A, oracle):
-    """Eight cells of 180 molecules each (the limit is 192): a neighbour cell never fits beside the
-    j carried over from the previous segment, so every segment boundary takes the path that first
-    evaluates the carried j on their own; groups hold one cell, i.e. three passes of up to 64."""
+    """Eight cells of 190 molecules each (the limit is 192): in the FP64 forward (segments of 192) a
+    neighbour cell never fits beside the j carried over from the previous segment, so segment
+    boundaries take the path that first evaluates the carried j on their own; groups hold one cell,
+    i.e. three passes of up to 64."""
     import torch
-    L, per = 12.0, 180
+    L, per = 14.0, 190
     sites = []
     for ci in range(2):
         for cj in range(2):
             for ck in range(2):
-                a, b, c = np.meshgrid(np.arange(6), np.arange(6), np.arange(5), indexing="ij")
-                s = np.stack([ci * 6 + 0.5 + a.ravel() * 1.0, cj * 6 + 0.5 + b.ravel() * 1.0,
-                              ck * 6 + 0.6 + c.ravel() * 1.2], axis=1)
+                a, b, c = np.meshgrid(np.arange(6), np.arange(6), np.arange(7), indexing="ij")
+                s = np.stack([ci * 7 + 0.55 + a.ravel() * (7.0 / 6.0), cj * 7 + 0.55 + b.ravel() * (7.0 / 6.0),
+                              ck * 7 + 0.5 + c.ravel() * 1.0], axis=1)[:per]
                 sites.append(s)
     x = np.vstack(sites)
     x = W.qround(x + np.random.default_rng(61).uniform(-0.1, 0.1, size=x.shape))
