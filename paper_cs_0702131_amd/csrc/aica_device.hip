@@ -942,7 +942,7 @@ static int ensure_groups(aica_dil *h, int64_t n) {
   if (h->groups_ready && h->groups_for_n == n) return AICA_OK;
   auto t0 = std::chrono::steady_clock::now();
   const double density = (double)n / h->geo.total_volume;
-  double target = 24.0;
+  double target = 27.0;  // expected molecules per group (measured best on the channel)
   if (const char *e = getenv("AICA_GROUP_TARGET")) target = std::max(1.0, atof(e));
   int rc = build_groups(h->geo, h->order, h->pairs, density, target, h->grp);
   if (rc) return rc;
