@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "LJ pair interactions/s (fwd, fwd+adjoint), FP32 vs FP64 GPU at stated error"
 FP32_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
+GAMMA = 0.1                  # weight of U in the adjoint's loss L = sum G.F + gamma U
 FP64_PEAK_TFLOPS = 78.6
 # algorithmic FLOPs (FMA = 2, reciprocal = 1): forward per pair inside the cut-off, per rejected
 # candidate (difference, squared distance, compare), adjoint per pair inside the cut-off
@@ -93,28 +94,30 @@ def timed_steps(A, d, x, sp, wl, G, precision, steps, warmup, adjoint=True):
         A.aica_bin(d, x)
         F, uw, npairs = A.aica_forces(d, x, sp, wl.eps, wl.sigma, precision=precision)
         if adjoint:
-            A.aica_forces_adjoint(d, x, G, 0.1, sp, wl.eps, wl.sigma, precision=precision)
+            A.aica_forces_adjoint(d, x, G, GAMMA, sp, wl.eps, wl.sigma, precision=precision)
     torch.cuda.synchronize()
     for k in ("pair_fwd", "pair_adj", "bin", "finalize"):
         d.profile_read(k, reset=True)
     d.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    gx = None
     for _ in range(steps):
         A.aica_bin(d, x)
         F, uw, npairs = A.aica_forces(d, x, sp, wl.eps, wl.sigma, precision=precision)
         if adjoint:
-            A.aica_forces_adjoint(d, x, G, 0.1, sp, wl.eps, wl.sigma, precision=precision)
+            gx = A.aica_forces_adjoint(d, x, G, GAMMA, sp, wl.eps, wl.sigma, precision=precision)[0]
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     d.profile(False)
     prof = {k: d.profile_read(k, reset=True) for k in ("pair_fwd", "pair_adj", "bin", "finalize")}
-    return t, prof, F, uw, int(npairs.item())
+    return t, prof, F, uw, int(npairs.item()), gx
 
 
-def cpu_baseline(wl, seconds_target, F32, F64, rng_seed=7):
+def cpu_baseline(wl, seconds_target, F32, F64, G, gx32, gx64, rng_seed=7):
     """Time the FP64 oracle on a bounded sample of rows (each row against every molecule and image),
-    extrapolate to all rows, and compare the GPU forces on the same rows."""
+    extrapolate to all rows, and compare the GPU forces on the same rows; then compare the GPU adjoint's
+    dL/dx with the oracle's on a third of those rows (not timed)."""
     from oracle import oracle as O
     O.lib()
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
@@ -136,7 +139,16 @@ def cpu_baseline(wl, seconds_target, F32, F64, rng_seed=7):
     errs = {}
     for name, F in (("fp32", F32), ("fp64", F64)):
         if F is not None:
-            errs[name] = float(np.sqrt(((F[rows] - Fr) ** 2).sum(1)).max() / rms)
+            errs[f"e_F_{name}"] = float(np.sqrt(((F[rows] - Fr) ** 2).sum(1)).max() / rms)
+    errs["e_F_rows"] = nrows
+    arows = rows[:max(1, nrows // 3)]
+    rg = O.adjoint_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, GAMMA, arows,
+                        rot=wl.rotations)
+    grms = np.sqrt((rg ** 2).mean())
+    for name, gx in (("fp32", gx32), ("fp64", gx64)):
+        if gx is not None:
+            errs[f"e_dLdx_{name}"] = float(np.abs(gx[arows] - rg).max() / grms)
+    errs["e_dLdx_rows"] = len(arows)
     return {"seconds": t, "rows": nrows, "t_full": t_full, "cores": cores, "row_pairs": int(cnt.sum()),
             "errors": errs}
 
@@ -198,17 +210,20 @@ def main():
         f"DIL candidates {dil_cand}, executed lane pairs {lane_pairs}")
 
     res = {}
-    t, prof, F32, uw32, npairs = timed_steps(A, d, x32, sp, wl, G32, "fp32", args.steps, args.warmup)
+    t, prof, F32, uw32, npairs, gx32 = timed_steps(A, d, x32, sp, wl, G32, "fp32", args.steps, args.warmup)
     res["fp32_fwd_adj"] = (t, prof)
     log(f"fp32 fwd+adj: {1e3 * t / args.steps:.3f} ms/step, npairs {npairs}")
-    t, prof, F32, uw32, _ = timed_steps(A, d, x32, sp, wl, G32, "fp32", args.steps, 1, adjoint=False)
+    gx32n = gx32.double().cpu().numpy()
+    t, prof, F32, uw32, _, _ = timed_steps(A, d, x32, sp, wl, G32, "fp32", args.steps, 1, adjoint=False)
     res["fp32_fwd"] = (t, prof)
     F32n = F32.double().cpu().numpy()
-    F64n = None
+    F64n = gx64n = None
     if not args.no_fp64:
-        t, prof, F64, uw64, npairs64 = timed_steps(A, d, x64, sp, wl, G64, "fp64", args.steps, args.warmup)
+        t, prof, F64, uw64, npairs64, gx64 = timed_steps(A, d, x64, sp, wl, G64, "fp64", args.steps, args.warmup)
         res["fp64_fwd_adj"] = (t, prof)
-        t, prof, F64, uw64, npairs64 = timed_steps(A, d, x64, sp, wl, G64, "fp64", args.steps, 1, adjoint=False)
+        gx64n = gx64.cpu().numpy()
+        t, prof, F64, uw64, npairs64, _ = timed_steps(A, d, x64, sp, wl, G64, "fp64", args.steps, 1,
+                                                      adjoint=False)
         res["fp64_fwd"] = (t, prof)
         F64n = F64.cpu().numpy()
         assert npairs64 == npairs, (npairs64, npairs)
@@ -238,13 +253,12 @@ def main():
     cpu = None
     errors = {"npairs": npairs}
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(wl, args.cpu_seconds, F32n, F64n)
+        cb = cpu_baseline(wl, args.cpu_seconds, F32n, F64n, G, gx32n, gx64n)
         cpu = {"value": npairs / cb["t_full"], "unit": "pair interactions/s", "cores": cb["cores"],
                "kind": "oracle",
                "sample": f"{cb['rows']} random rows of {wl.n} (each against all molecules and images, "
                          f"{cb['seconds']:.1f}s), extrapolated linearly to all rows"}
-        errors.update({f"e_F_{k}": v for k, v in cb["errors"].items()})
-        errors["e_F_rows"] = cb["rows"]
+        errors.update(cb["errors"])
     if F64n is not None:
         errors["e_F_fp32_vs_fp64_gpu"] = float(np.sqrt(((F32n - F64n) ** 2).sum(1)).max()
                                                / np.sqrt((F64n ** 2).sum(1).mean()))

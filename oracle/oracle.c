@@ -400,6 +400,51 @@ int64_t oc_pairs(int64_t n, const double *x, double rc, int32_t nper, const doub
  * Row a collects dL/dx_a = sum_b dl/dd(a,b) (each pair seen from both rows: from b's row the pair is
  * (b, a, T^-1) with d and G_a - G_b' both mapped by -R^T, and dl/dd maps the same way, so that row's
  * term is the gradient with respect to x_b); parameter sums take half per row. */
+/* Row a of the adjoint: gxa = dL/dx_a; with pe, ps non-NULL, also the row's halves of the
+ * species-pair sums of dl/deps_ab and dl/dsig_ab ([64], indexed 8 sp_a + sp_b) and of L. */
+static void oc_adjoint_row(int64_t a, int64_t n, const double *x, const int32_t *sp, const double *eps,
+                           const double *sig, double rc2, int nimg, const oc_xf *img, const double *G,
+                           double gamma, double *gxa, double *pe, double *ps, double *pl) {
+  double v0 = 0, v1 = 0, v2 = 0, la = 0;
+  for (int64_t b = 0; b < n; ++b) {
+    double e, sg;
+    oc_mix(eps, sig, sp[a], sp[b], &e, &sg);
+    for (int k = 0; k < nimg; ++k) {
+      if (b == a && oc_is_zero(img[k].n)) continue;
+      double xb[3], gb[3];
+      oc_xf_apply(&img[k], x + 3 * b, xb);
+      oc_xf_rotate(&img[k], G + 3 * b, gb);
+      double dg0 = G[3 * a] - gb[0], dg1 = G[3 * a + 1] - gb[1], dg2 = G[3 * a + 2] - gb[2];
+      double d0 = x[3 * a] - xb[0];
+      double d1 = x[3 * a + 1] - xb[1];
+      double d2 = x[3 * a + 2] - xb[2];
+      double s = d0 * d0 + d1 * d1 + d2 * d2;
+      if (!(s < rc2)) continue;
+      double sr2 = sg * sg / s, sr6 = sr2 * sr2 * sr2, sr12 = sr6 * sr6;
+      double u = 4.0 * e * (sr12 - sr6);
+      double g = 24.0 * e * (2.0 * sr12 - sr6) / s;
+      double gp = 24.0 * e * (-14.0 * sr12 + 4.0 * sr6) / (s * s);
+      double gd = dg0 * d0 + dg1 * d1 + dg2 * d2;
+      double c = 2.0 * gp * gd - gamma * g;
+      v0 += g * dg0 + c * d0;
+      v1 += g * dg1 + c * d1;
+      v2 += g * dg2 + c * d2;
+      if (!pe) continue;
+      double l = gd * g + gamma * u;
+      la += 0.5 * l;
+      double dgds = (24.0 * e / sg) * (24.0 * sr12 - 6.0 * sr6) / s;
+      double duds = (24.0 * e / sg) * (2.0 * sr12 - sr6);
+      int t = sp[a] * 8 + sp[b];
+      pe[t] += 0.5 * l / e;
+      ps[t] += 0.5 * (gd * dgds + gamma * duds);
+    }
+  }
+  gxa[0] = v0;
+  gxa[1] = v1;
+  gxa[2] = v2;
+  if (pl) *pl = la;
+}
+
 int oc_adjoint(int64_t n, const double *x, const int32_t *sp, int32_t nsp, const double *eps, const double *sig,
                double rc, int32_t nper, const double *lat, const double *rot, const double *G, double gamma,
                double *gx, double *geps, double *gsig, double *L) {
@@ -416,45 +461,8 @@ int oc_adjoint(int64_t n, const double *x, const int32_t *sp, int32_t nsp, const
   double *ps = (double *)calloc((size_t)(n > 0 ? n : 1) * 64, sizeof(double));
   double *pl = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
 #pragma omp parallel for schedule(static)
-  for (int64_t a = 0; a < n; ++a) {
-    double v0 = 0, v1 = 0, v2 = 0, la = 0;
-    for (int64_t b = 0; b < n; ++b) {
-      double e, sg;
-      oc_mix(eps, sig, sp[a], sp[b], &e, &sg);
-      for (int k = 0; k < nimg; ++k) {
-        if (b == a && oc_is_zero(img[k].n)) continue;
-        double xb[3], gb[3];
-        oc_xf_apply(&img[k], x + 3 * b, xb);
-        oc_xf_rotate(&img[k], G + 3 * b, gb);
-        double dg0 = G[3 * a] - gb[0], dg1 = G[3 * a + 1] - gb[1], dg2 = G[3 * a + 2] - gb[2];
-        double d0 = x[3 * a] - xb[0];
-        double d1 = x[3 * a + 1] - xb[1];
-        double d2 = x[3 * a + 2] - xb[2];
-        double s = d0 * d0 + d1 * d1 + d2 * d2;
-        if (!(s < rc2)) continue;
-        double sr2 = sg * sg / s, sr6 = sr2 * sr2 * sr2, sr12 = sr6 * sr6;
-        double u = 4.0 * e * (sr12 - sr6);
-        double g = 24.0 * e * (2.0 * sr12 - sr6) / s;
-        double gp = 24.0 * e * (-14.0 * sr12 + 4.0 * sr6) / (s * s);
-        double gd = dg0 * d0 + dg1 * d1 + dg2 * d2;
-        double c = 2.0 * gp * gd - gamma * g;
-        v0 += g * dg0 + c * d0;
-        v1 += g * dg1 + c * d1;
-        v2 += g * dg2 + c * d2;
-        double l = gd * g + gamma * u;
-        la += 0.5 * l;
-        double dgds = (24.0 * e / sg) * (24.0 * sr12 - 6.0 * sr6) / s;
-        double duds = (24.0 * e / sg) * (2.0 * sr12 - sr6);
-        int t = sp[a] * 8 + sp[b];
-        pe[64 * a + t] += 0.5 * l / e;
-        ps[64 * a + t] += 0.5 * (gd * dgds + gamma * duds);
-      }
-    }
-    gx[3 * a] = v0;
-    gx[3 * a + 1] = v1;
-    gx[3 * a + 2] = v2;
-    pl[a] = la;
-  }
+  for (int64_t a = 0; a < n; ++a)
+    oc_adjoint_row(a, n, x, sp, eps, sig, rc2, nimg, img, G, gamma, gx + 3 * a, pe + 64 * a, ps + 64 * a, pl + a);
   double se[64], ss[64];
   memset(se, 0, sizeof se);
   memset(ss, 0, sizeof ss);
@@ -490,6 +498,26 @@ int oc_adjoint(int64_t n, const double *x, const int32_t *sp, int32_t nsp, const
   free(pe);
   free(ps);
   free(pl);
+  free(img);
+  return OC_OK;
+}
+
+/* dL/dx on selected rows only (each against all n molecules and images): the sampled check of the
+ * adjoint for workloads too large for all pairs.  gx is [nrows][3]. */
+int oc_adjoint_rows(int64_t n, const double *x, const int32_t *sp, int32_t nsp, const double *eps,
+                    const double *sig, double rc, int32_t nper, const double *lat, const double *rot,
+                    const double *G, double gamma, int64_t nrows, const int64_t *rows, double *gx) {
+  int nimg;
+  oc_xf *img = oc_images_for(nper, lat, rot, rc, 0, &nimg);
+  if (!img) return OC_E_INVAL;
+  if (nsp < 1 || nsp > 8) {
+    free(img);
+    return OC_E_INVAL;
+  }
+  double rc2 = rc * rc;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < nrows; ++r)
+    oc_adjoint_row(rows[r], n, x, sp, eps, sig, rc2, nimg, img, G, gamma, gx + 3 * r, NULL, NULL, NULL);
   free(img);
   return OC_OK;
 }

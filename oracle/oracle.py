@@ -43,6 +43,8 @@ def lib():
         L.oc_pairs.restype = i64
         L.oc_adjoint.argtypes = [i64, p, p, i32, p, p, f64, i32, p, p, p, f64, p, p, p, p]
         L.oc_adjoint.restype = C.c_int
+        L.oc_adjoint_rows.argtypes = [i64, p, p, i32, p, p, f64, i32, p, p, p, f64, i64, p, p]
+        L.oc_adjoint_rows.restype = C.c_int
         mesh_args = [i64, p, i64, p, p, p, p, i64]
         L.oc_dil.argtypes = mesh_args + [i32, p, p, f64, f64, i32, i64, p, p, p]
         L.oc_dil.restype = i64
@@ -163,6 +165,22 @@ def adjoint(x, species, eps, sigma, rcut, lattice, G, gamma, rot=None):
     if rc != 0:
         raise ValueError(f"oc_adjoint failed ({rc})")
     return gx, ge, gs, L.value
+
+
+def adjoint_rows(x, species, eps, sigma, rcut, lattice, G, gamma, rows, rot=None):
+    """dL/dx on the given rows only (each against all molecules and images), [len(rows), 3]."""
+    x = _c(x, np.float64)
+    sp = _c(species, np.int32)
+    eps, sig = _c(eps, np.float64), _c(sigma, np.float64)
+    lat, rot, nper = _lat(lattice, rot)
+    G = _c(G, np.float64)
+    rows = _c(rows, np.int64)
+    gx = np.zeros((len(rows), 3))
+    rc = lib().oc_adjoint_rows(len(x), _ptr(x), _ptr(sp), len(eps), _ptr(eps), _ptr(sig), float(rcut), nper,
+                               _ptr(lat), _rp(rot), _ptr(G), float(gamma), len(rows), _ptr(rows), _ptr(gx))
+    if rc != 0:
+        raise ValueError(f"oc_adjoint_rows failed ({rc})")
+    return gx
 
 
 def loss(x, species, eps, sigma, rcut, lattice, G, gamma, rot=None):

@@ -1,7 +1,8 @@
 """The benchmark's workload at full size (6,683,992 molecules, 4,312,968 cells of the graded jittered
 channel), in the launch configuration the benchmark times: FP32 and FP64 forces on sampled rows
 against the oracle (each row summed over every molecule and image), equal pair counts in both
-precisions, and the adjoint's invariants (translation invariance of L, eps-homogeneity)."""
+precisions, dL/dx of the adjoint on sampled rows against the oracle in both precisions, and the
+adjoint's invariants (translation invariance of L, eps-homogeneity)."""
 import sys
 import time
 
@@ -69,3 +70,16 @@ def test_channel_full_size(A, oracle):
     _note(f"  adjoint fp32: |sum dL/dx| / sum |dL/dx| {tinv:.3e}, eps-homogeneity {homog:.3e} ({time.time() - t0:.1f}s)")
     assert tinv < 1e-5
     assert homog < 1e-5
+    # dL/dx on sampled rows against the oracle (each row summed over every molecule and image)
+    arows = rows[:128]
+    rg = oracle.adjoint_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam, arows)
+    grms = np.sqrt((rg ** 2).mean())
+    err32 = np.abs(gx[arows] - rg).max() / grms
+    x = torch.tensor(wl.x, dtype=torch.float64, device="cuda")
+    A.aica_bin(d, x)
+    g64, _, _ = A.aica_forces_adjoint(d, x, torch.tensor(G, dtype=torch.float64, device="cuda"), gam, None,
+                                      wl.eps, wl.sigma, precision="fp64")
+    err64 = np.abs(g64.cpu().numpy()[arows] - rg).max() / grms
+    _note(f"  adjoint on {len(arows)} rows: fp32 {err32:.3e}, fp64 {err64:.3e} ({time.time() - t0:.1f}s)")
+    assert err32 < 1e-5
+    assert err64 < 1e-12

@@ -324,6 +324,22 @@ def test_adjoint_position_fd_and_invariants(oracle):
     assert checked >= 16
 
 
+def test_adjoint_rows(oracle):
+    # the sampled-row adjoint used at sizes the full adjoint cannot reach: with G = 0 it is gamma grad U
+    # = -gamma F on those rows (forces pinned on their own), and for any G it is the full adjoint's rows
+    wl, G = _adj_case()
+    rows = np.array([0, 7, 7, 119, 53])
+    F = oracle.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, rows)[0]
+    g0 = oracle.adjoint_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic,
+                             np.zeros_like(G), 0.5, rows)
+    assert np.allclose(g0, -0.5 * F, rtol=0, atol=1e-13 * np.abs(F).max())
+    gx = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, 0.1)[0]
+    gr = oracle.adjoint_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, 0.1, rows)
+    assert np.array_equal(gr, gx[rows])
+    assert oracle.adjoint_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, 0.1,
+                               np.zeros(0, np.int64)).shape == (0, 3)
+
+
 def test_adjoint_hessian_symmetry(oracle):
     wl, G = _adj_case()
     V = W.qround(np.random.default_rng(34).standard_normal((wl.n, 3)))
@@ -482,6 +498,15 @@ def test_wedge_adjoint_equals_whole_annulus(oracle, wedge_small):
     # L itself: sum G.F + gamma U from the forces
     F, U, _, _ = oracle.forces(w.x, w.species, w.eps, w.sigma, w.rcut, w.lattice, rot=w.rotations)
     assert abs(L - (np.sum(G * F) + 0.3 * U)) <= 1e-12 * (abs(L) + abs(U))
+
+
+def test_wedge_adjoint_rows(oracle, wedge_small):
+    w = wedge_small
+    G = np.random.default_rng(6).standard_normal((w.n, 3))
+    gx = oracle.adjoint(w.x, w.species, w.eps, w.sigma, w.rcut, w.lattice, G, 0.3, rot=w.rotations)[0]
+    rows = np.arange(0, w.n, 37)
+    gr = oracle.adjoint_rows(w.x, w.species, w.eps, w.sigma, w.rcut, w.lattice, G, 0.3, rows, rot=w.rotations)
+    assert np.array_equal(gr, gx[rows])
 
 
 def test_wedge_pairs_map_to_annulus_pairs(oracle, wedge_small):
