@@ -264,6 +264,8 @@ def main():
                                                / np.sqrt((F64n ** 2).sum(1).mean()))
         errors["dU_fp32_vs_fp64"] = float(abs(uw32[0].item() - uw64[0].item()) / abs(uw64[0].item()))
         errors["dW_fp32_vs_fp64"] = float(abs(uw32[1].item() - uw64[1].item()) / abs(uw64[1].item()))
+        # every row of dL/dx (the FP64 path matches the oracle to ~1e-15 on the sampled rows)
+        errors["e_dLdx_fp32_vs_fp64_gpu"] = float(np.abs(gx32n - gx64n).max() / np.sqrt((gx64n ** 2).mean()))
 
     out = {"metric": METRIC, "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": K,
            "warmup": args.warmup, "ms_per_step": 1e3 * t_main / K, "higher_is_better": True, "scaling": "weak",
