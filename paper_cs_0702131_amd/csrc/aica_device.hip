@@ -658,7 +658,13 @@ struct LaneLJ {
 };
 
 __device__ __forceinline__ float fast_rcp(float s) { return __builtin_amdgcn_rcpf(s); }
-__device__ __forceinline__ double fast_rcp(double s) { return 1.0 / s; }
+// FP64: the hardware reciprocal refined by two Newton steps (about 1 ulp, against the ten instructions of
+// a correctly rounded division; the FP64 path's bar is 1e-12 of the result)
+__device__ __forceinline__ double fast_rcp(double s) {
+  double r = __builtin_amdgcn_rcp(s);
+  r = fma(r, fma(-s, r, 1.0), r);
+  return fma(r, fma(-s, r, 1.0), r);
+}
 
 template <typename T>
 __device__ __forceinline__ T far_i() { return (T)1e15; }
