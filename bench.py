@@ -87,6 +87,26 @@ def measured_traffic(kernel, workload):
     return rows.get(kernel)
 
 
+PAIR_KERNELS = {"pair_fwd": "k_pair<float, 0, 0, true, false>", "pair_adj": "k_pair<float, 0, 2, true, false>"}
+
+
+def measured_valu_issue(kernel, workload):
+    """Executed VALU instructions of `kernel` over its launch duration as a fraction of the chip's VALU issue
+    peak, from the committed counter summary, or None when it is missing or was taken on other kernel
+    sources."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.txt")
+    if not os.path.exists(path) or kernel not in PAIR_KERNELS:
+        return None
+    digest, frac = None, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("# kernel sources sha256"):
+                digest = line.split(":")[-1].strip()
+            elif line.strip().startswith(PAIR_KERNELS[kernel]):
+                frac = float(line.split()[-1])
+    return frac if digest == kernel_digest() else None
+
+
 def timed_steps(A, d, x, sp, wl, G, precision, steps, warmup, adjoint=True):
     import torch
     st = torch.cuda.current_stream()
@@ -247,6 +267,7 @@ def main():
     traffic = measured_traffic(kname, args.workload)
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic, "traffic_unit": "bytes per launch",
+                "valu_issue_frac": measured_valu_issue(kname, args.workload),
                 "kernel": kname,
                 "kernel_ms": kms, "algorithmic_flop": flops}
 
