@@ -11,27 +11,6 @@ constexpr int kRotFlag = 64;     // added to an entry's image code when its refe
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = 64 * kWavesPerBlock;
 
-// Rotations inside a 16-lane DPP row: lane c receives the value of lane (c + 1) & 15 (row_ror:15),
-// or of lane (c + 7) & 15 (row_ror:9).
-__device__ __forceinline__ float ror15(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x12F, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float ror9(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x129, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double ror15(double v) {
-  int2 p = __builtin_bit_cast(int2, v);
-  p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x12F, 0xF, 0xF, false);
-  p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x12F, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, p);
-}
-__device__ __forceinline__ double ror9(double v) {
-  int2 p = __builtin_bit_cast(int2, v);
-  p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x129, 0xF, 0xF, false);
-  p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x129, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, p);
-}
-
 // Error-free transformation a + b = s + e (Knuth's TwoSum).
 template <typename T>
 __device__ __forceinline__ void two_sum(T a, T b, T &s, T &e) {
