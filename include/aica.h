@@ -159,7 +159,10 @@ int aica_forces(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, 
  * grad_energy: gamma (host scalar).  grad_pos_dev: device [n][3] compute dtype,
  * overwritten.  grad_eps_dev, grad_sigma_dev: device double[n_species],
  * overwritten (either may be NULL).  Same preconditions as aica_forces;
- * params->n_species must be 1 or 2.
+ * params->n_species must be 1 or 2.  Precision: with AICA_FP32 the pair terms
+ * (which carry up to r^-16) are good to about 1e-6 of themselves, so a row whose
+ * dL/dx is dominated by a contact closer than about 1 sigma can differ from the
+ * exact value by more than 1e-5 of the rms of dL/dx; AICA_FP64 has no such limit.
  * Errors: AICA_E_INVAL (also for more than two species), AICA_E_NOMEM, AICA_E_HIP. */
 int aica_forces_adjoint(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
                         const void *grad_forces_dev, double grad_energy, void *grad_pos_dev, double *grad_eps_dev,
