@@ -440,7 +440,7 @@ def channel_mesh(Lx, Ly, Lz, hx, hy_wall, hy_mid, hz, jitter, rng):
 def config5(seed=5, scale=1.0, shuffle=True):
     """400x200x100 channel periodic in x,z with walls in y; graded jittered hex mesh
     of about 4M cells (y spacing 1.0 at the walls to 2.5 at the centre); FCC
-    238x119x59 unit cells, N = 6,683,672 (density 0.836).  scale < 1 shrinks
+    238x119x59 unit cells, N = 6,683,992 (density 0.836).  scale < 1 shrinks
     every length (and N) for smaller tests."""
     Lx, Ly, Lz = (float(qround(v * scale)) for v in (400.0, 200.0, 100.0))
     hxz = 1.07
