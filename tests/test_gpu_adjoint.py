@@ -130,3 +130,35 @@ def test_full_size_identities(A):
               f"eps-homogeneity {abs((wl.eps * ge).sum() - L) / abs(L):.3e}")
         assert np.abs(gx.sum(0)).max() < tol * np.abs(gx).sum(0).max()
         assert abs((wl.eps * ge).sum() - L) < tol * abs(L)
+
+
+def test_one_species_with_scaled_parameters(A, oracle):
+    # one species with eps and sigma far from 1 (the one-species kernels apply 24 eps once per pass and
+    # take sigma^2 from the table): forces, U, W, pair count and the adjoint against the oracle
+    import dataclasses
+
+    import torch
+    base = W.small_random(n_mesh=(4, 3, 4), L=(8.5, 7.5, 9.0), N=200, seed=37, min_sep=1.4)
+    wl = dataclasses.replace(base, eps=np.array([0.7]), sigma=np.array([1.3]))
+    G = W.qround(np.random.default_rng(38).standard_normal((wl.n, 3)))
+    gam = 0.2
+    Fr, Ur, Wr, nr = oracle.forces(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic)
+    rx, re, rs, rL = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
+    d = A.DIL(wl.mesh, wl.rcut)
+    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-5)):
+        x = torch.tensor(wl.x, dtype=dt, device="cuda")
+        A.aica_bin(d, x)
+        F, uw, npairs = A.aica_forces(d, x, None, wl.eps, wl.sigma, precision=prec)
+        gx, ge, gs = A.aica_forces_adjoint(d, x, torch.tensor(G, dtype=dt, device="cuda"), gam, None, wl.eps,
+                                           wl.sigma, precision=prec)
+        torch.cuda.synchronize()
+        F = F.double().cpu().numpy()
+        eF = np.sqrt(((F - Fr) ** 2).sum(1)).max() / np.sqrt((Fr ** 2).sum(1).mean())
+        ex = rel_max(gx.double().cpu().numpy(), rx)
+        ee = abs(ge.cpu().numpy()[0] - re[0]) / abs(re[0])
+        es = abs(gs.cpu().numpy()[0] - rs[0]) / abs(rs[0])
+        _note(f"eps 0.7 sigma 1.3 {prec}: e_F {eF:.2e} dU {abs(uw[0].item() - Ur) / abs(Ur):.2e} "
+              f"dx {ex:.2e} deps {ee:.2e} dsig {es:.2e}")
+        assert int(npairs.cpu()[0]) == nr
+        assert eF < tol and ex < tol and ee < tol and es < tol
+        assert abs(uw[0].item() - Ur) <= tol * abs(Ur) and abs(uw[1].item() - Wr) <= tol * abs(Wr)
