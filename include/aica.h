@@ -137,7 +137,8 @@ int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, v
  *   U = sum u, W = sum g |d|^2 (virial sum r.F), npairs = number of pairs.
  * pos_dev must be the array last passed to aica_bin (same pointer, dtype and
  * n; otherwise AICA_E_INVAL).  species_dev: device int32 [n] in 0..n_species-1,
- * or NULL for all-zero.  forces_dev: device [n][3] in the compute precision's
+ * or NULL for all-zero; the ids are not checked (that would cost a synchronisation):
+ * an id below 0 is taken as 0 and one above n_species-1 as n_species-1.  forces_dev: device [n][3] in the compute precision's
  * dtype (float for AICA_FP32, double for AICA_FP64), caller order, overwritten.
  * uw_dev: device double[2] = {U, W}, overwritten; npairs_dev: device int64,
  * overwritten.  Either may be NULL.  Results are deterministic (fixed

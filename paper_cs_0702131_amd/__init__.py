@@ -134,9 +134,18 @@ def _species_ptr(species, pos):
     if species is None:
         return C.c_void_p(0)
     import torch
-    if species.dtype != torch.int32 or not species.is_cuda or species.shape[0] != pos.shape[0]:
-        raise ValueError("species must be an int32 device tensor of length n")
+    if (species.dtype != torch.int32 or not species.is_cuda or species.device != pos.device
+            or species.dim() != 1 or species.shape[0] != pos.shape[0] or not species.is_contiguous()):
+        raise ValueError("species must be a contiguous int32 tensor of length n on the positions' device")
     return C.c_void_p(species.data_ptr())
+
+
+def _check_grad_forces(grad_forces, pos):
+    """The upstream gradient G must be an [n, 3] tensor on the positions' device (a host tensor would hand
+    the kernels a host pointer; fewer rows would be read past their end)."""
+    if (not hasattr(grad_forces, "is_cuda") or not grad_forces.is_cuda or grad_forces.device != pos.device
+            or grad_forces.dim() != 2 or tuple(grad_forces.shape) != (pos.shape[0], 3)):
+        raise ValueError("grad_forces must be an [n, 3] tensor on the positions' device")
 
 
 def aica_forces(dil: DIL, pos, species=None, eps=(1.0,), sigma=(1.0,), rcut=None, precision="fp32",
@@ -160,6 +169,7 @@ def aica_forces_adjoint(dil: DIL, pos, grad_forces, grad_energy, species=None, e
     """dL/dx [n,3], dL/deps [n_species], dL/dsigma [n_species] for L = sum G.F + gamma U."""
     import torch
     _check_pos(pos)
+    _check_grad_forces(grad_forces, pos)
     p, keep = _params(dil.rcut if rcut is None else rcut, eps, sigma, precision, True)
     dt = torch.float32 if p.precision == AICA_FP32 else torch.float64
     G = grad_forces.to(dtype=dt).contiguous()

@@ -190,3 +190,29 @@ def test_errors_referring_transforms(A):
     with pytest.raises(A.AicaError) as e:
         A.DIL(m, 2.5)
     assert e.value.code == A.AICA_E_INVAL
+
+
+class _FakeTensor:
+    """A stand-in with the attributes the binding's checks read (no GPU here)."""
+
+    def __init__(self, shape, is_cuda=True, device="cuda:0"):
+        self.shape = tuple(shape)
+        self.is_cuda = is_cuda
+        self.device = device
+
+    def dim(self):
+        return len(self.shape)
+
+
+def test_adjoint_rejects_bad_grad_forces():
+    import paper_cs_0702131_amd as pkg
+    pos = _FakeTensor((10, 3))
+    pkg._check_grad_forces(_FakeTensor((10, 3)), pos)          # accepted
+    for bad in (_FakeTensor((10, 3), is_cuda=False, device="cpu"),  # host memory
+                _FakeTensor((10, 3), device="cuda:1"),               # another device
+                _FakeTensor((9, 3)),                                  # too few rows
+                _FakeTensor((10, 2)),                                 # wrong width
+                _FakeTensor((30,)),                                   # flat
+                np.zeros((10, 3))):                                   # not a tensor
+        with pytest.raises(ValueError):
+            pkg._check_grad_forces(bad, pos)

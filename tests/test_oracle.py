@@ -178,6 +178,104 @@ def test_cell_distance_special_cases(oracle):
     assert abs(oracle.cell_distance(m, c(0, 0, 0), c(2, 0, 2), (0, 0.5, 0)) - math.sqrt(2)) < 1e-14
 
 
+def _two_tets(A, B):
+    """A mesh of two separate tetrahedral cells with vertices A[4] and B[4] (every face a boundary face,
+    loops oriented out of their cell)."""
+    pts = np.concatenate([np.asarray(A, float), np.asarray(B, float)])
+    loops, owner = [], []
+    for cell in range(2):
+        tv = [4 * cell + k for k in range(4)]
+        for (a, b, c, d) in ((0, 1, 2, 3), (0, 1, 3, 2), (0, 2, 3, 1), (1, 2, 3, 0)):
+            tri = [tv[a], tv[b], tv[c]]
+            nrm = np.cross(pts[tri[1]] - pts[tri[0]], pts[tri[2]] - pts[tri[0]])
+            if np.dot(nrm, pts[tv[d]] - pts[tri[0]]) > 0:
+                tri = tri[::-1]
+            loops.append(tri)
+            owner.append(cell)
+    F = len(owner)
+    return W.Mesh(points=pts, face_off=np.arange(F + 1, dtype=np.int64) * 3,
+                  face_pts=np.array(loops, dtype=np.int32).ravel(), owner=np.array(owner, np.int32),
+                  neighbour=np.full(F, -1, np.int32), n_cells=2)
+
+
+def _rotation(seed):
+    q, r = np.linalg.qr(np.random.default_rng(seed).standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    return q if np.linalg.det(q) > 0 else -q
+
+
+def test_cell_distance_skew_edges(oracle):
+    """Two tetrahedra whose closest points are interior points of two skew edges (the edge (0,0,0)-(2,0,0)
+    of one, the edge (1,-1,h)-(1,1,h) of the other): the distance is h, and no vertex, no vertex-face foot
+    point and no edge end comes closer (the nearest of those is sqrt(1 + h^2) away).  The configuration is
+    turned by generic rotations, so no coordinate axis helps.  Sec. 2.2: closest approach of two cells."""
+    for h in (0.25, 0.5, 1.7):
+        A = [(0, 0, 0), (2, 0, 0), (1, 1, -2), (1, -1, -2)]
+        B = [(1, -1, h), (1, 1, h), (0, 0, h + 2), (2, 0, h + 2)]
+        for seed in (0, 1, 2):
+            R = _rotation(seed)
+            m = _two_tets(np.asarray(A, float) @ R.T, np.asarray(B, float) @ R.T)
+            assert abs(oracle.cell_distance(m, 0, 1) - h) < 1e-12 * (1 + h), (h, seed)
+            # the same through the transform argument (cell 1 moved back by R^T, then forward again)
+            m2 = _two_tets(np.asarray(A, float) @ R.T, np.asarray(B, float))
+            assert abs(oracle.cell_distance(m2, 0, 1, rot=R) - h) < 1e-12 * (1 + h), (h, seed)
+
+
+def test_cell_distance_vertex_over_face_interior(oracle):
+    """A vertex of one tetrahedron straight above an interior point of a face of the other, along the
+    face's normal at height h (the foot (1.7, 0.9) lies inside one of the face's fan triangles, away from
+    the fan's spokes): the distance is h; the nearest edge of that face is farther than 0.45.  Generic
+    rotations again.  Sec. 2.2: closest approach of two cells."""
+    for h in (0.2, 0.6, 1.3):
+        A = [(0, 0, 0), (4, 0, 0), (0, 4, 0), (0.5, 0.5, -3)]
+        p = np.array([1.7, 0.9, h])
+        B = [p, p + (1, 0.2, 3), p + (-0.3, 1, 3), p + (-0.8, -0.9, 3)]
+        for seed in (3, 4, 5):
+            R = _rotation(seed)
+            m = _two_tets(np.asarray(A, float) @ R.T, np.asarray(B, float) @ R.T)
+            assert abs(oracle.cell_distance(m, 0, 1) - h) < 1e-12 * (1 + h), (h, seed)
+
+
+def test_cell_distance_random_tets_against_convex_program(oracle):
+    """Separated random tetrahedra: the closest distance of two convex cells is the minimum of
+    |sum l_i a_i - sum m_j b_j| over the two simplices of weights, solved here as a small convex program
+    (scipy SLSQP), independent of the oracle's triangle-pair routines."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(77)
+    for trial in range(40):
+        A = rng.uniform(-1, 1, (4, 3))
+        B = rng.uniform(-1, 1, (4, 3)) + rng.uniform(-1, 1, 3) * 0 + np.array([rng.uniform(2.2, 3.5), 0, 0])
+        R = _rotation(100 + trial)
+        A, B = A @ R.T, B @ R.T
+        if abs(np.dot(np.cross(A[1] - A[0], A[2] - A[0]), A[3] - A[0])) < 0.05:
+            continue
+        if abs(np.dot(np.cross(B[1] - B[0], B[2] - B[0]), B[3] - B[0])) < 0.05:
+            continue
+        m = _two_tets(A, B)
+
+        def f(w):
+            d = w[:4] @ A - w[4:] @ B
+            return d @ d
+
+        def jac(w):
+            d = w[:4] @ A - w[4:] @ B
+            return np.concatenate([2 * A @ d, -2 * B @ d])
+
+        cons = [{"type": "eq", "fun": lambda w: w[:4].sum() - 1, "jac": lambda w: np.r_[np.ones(4), np.zeros(4)]},
+                {"type": "eq", "fun": lambda w: w[4:].sum() - 1, "jac": lambda w: np.r_[np.zeros(4), np.ones(4)]}]
+        best = np.inf
+        for start in range(4):
+            w0 = np.full(8, 0.25)
+            w0[start] += 0.5
+            w0[:4] /= w0[:4].sum()
+            r = minimize(f, w0, jac=jac, bounds=[(0, 1)] * 8, constraints=cons, method="SLSQP",
+                         options={"ftol": 1e-15, "maxiter": 500})
+            best = min(best, r.fun)
+        ref = np.sqrt(max(best, 0.0))
+        got = oracle.cell_distance(m, 0, 1)
+        assert abs(got - ref) < 1e-6, (trial, got, ref)
+
+
 def test_point_location_uniform(oracle):
     nodes = np.linspace(0, 6.0, 4)
     m = W.hex_mesh(nodes, nodes, nodes, shuffle_seed=4)
