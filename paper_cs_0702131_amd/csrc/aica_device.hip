@@ -674,6 +674,7 @@ __device__ __forceinline__ T far_j() { return (T)-1e15; }
 }  // namespace
 
 #include "aica_pair.inc"
+#include "aica_adjoint_pair.inc"
 
 namespace {
 
@@ -1133,7 +1134,6 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   }
   // the unlocated count is read with the other counts below (one synchronisation per binning); an
   // unlocated molecule is left out of the occupancy and of the permutation
-  hipLaunchKernelGGL(k_max_count, dim3(grid1d(nc, 256)), dim3(256), 0, st, h->d_count.as<int32_t>(), nc, status);
   if ((rc = scan_exclusive<int32_t>(h, h->d_count.as<int32_t>(), nc, h->d_cell_start.as<int32_t>(), st))) return rc;
   if (n > 0)
     hipLaunchKernelGGL(k_scatter, dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_cell_of.as<int32_t>(), trav, n,
@@ -1153,15 +1153,12 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   HIPCHK(hipMemcpyAsync(&jt, h->d_slot_base.as<int64_t>() + nc, 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(stat, status, sizeof stat, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  const unsigned long long unl = stat[0], over = stat[1];
+  const unsigned long long unl = stat[0];
   if (unl > 0) return fail(AICA_E_UNLOCATED, std::to_string(unl) + " molecule(s) lie in no mesh cell");
   h->located[1] = 0;
   for (int k = 0; k < kRouteSlots; ++k) h->located[1] += (int64_t)stat[8 + k];
   h->located[2] = (int64_t)stat[2];
   h->located[0] = n - h->located[1] - h->located[2];
-  if (over > 0)
-    return fail(AICA_E_INVAL, std::to_string(over) + " cell(s) hold more than " + std::to_string(kLCap) +
-                                  " molecules; refine the mesh");
   if (jt >= (1LL << 31)) return fail(AICA_E_NOMEM, "reaction slots exceed 2^31; split the system");
   h->perm_n = n;  // d_perm holds this binning's permutation
   h->jtotal = jt;
@@ -1221,49 +1218,36 @@ static int prepare_jpart(aica_dil *h, size_t bytes, hipStream_t st) {
 }
 
 template <typename T, int MODE>
-static int launch_pair(aica_dil *h, const LJTab &tab, const AdjTab &at, bool comp, hipStream_t st, int64_t cap,
-                       unsigned long long *pcount) {
+static int launch_pair(aica_dil *h, const LJTab &tab, bool comp, hipStream_t st, int64_t cap,
+                       unsigned long long *pcount, int32_t *mol_count = nullptr) {
   using V4 = typename Vec4<T>::type;
   const int64_t ng = h->grp.ng;
   constexpr int NW = pair_waves(sizeof(T));
   const int64_t nblocks = (ng + NW - 1) / NW;
   const int64_t padded = ((nblocks + 7) / 8) * 8;
   const V4 *pos = h->d_pos.as<V4>();
-  const V4 *gs = MODE == 2 ? h->d_gG.as<V4>() : nullptr;
   const V4 *ev = sizeof(T) == 4 ? (const V4 *)h->d_e_vec32.p : (const V4 *)h->d_e_vec64.p;
   T *jpart = MODE == 1 ? nullptr : h->d_jpart.as<T>();
   T *own = MODE == 1 ? nullptr : h->d_own.as<T>();
-  double *gpart = MODE == 0 ? h->d_gpart.as<double>() : (MODE == 2 ? h->d_gpar.as<double>() : nullptr);
+  double *gpart = MODE == 0 ? h->d_gpart.as<double>() : nullptr;
   unsigned long long *gnp = MODE == 0 ? h->d_gnp.as<unsigned long long>() : nullptr;
-  int32_t *pairs_out = MODE == 1 ? h->d_pairs.as<int32_t>() : nullptr;
+  int32_t *pairs_out = (MODE == 1 && cap >= 0) ? h->d_pairs.as<int32_t>() : nullptr;  // cap < 0: counts only
   // rotating referral: FP64 rotations and offsets for both precisions (the referred position is rounded once)
   const double *rot = h->geo.has_rot ? h->d_rot64.as<double>() : nullptr;
   const double4 *evd = h->geo.has_rot ? h->d_e_vec64.as<double4>() : nullptr;
   const int nsp = tab.nsp;
 #define AICA_LAUNCH_R(MIX, COMP, ROT)                                                                              \
-  hipLaunchKernelGGL((k_pair<T, MIX, MODE, COMP, ROT>), dim3((unsigned)padded), dim3(64 * NW), 0, st, pos, gs,     \
+  hipLaunchKernelGGL((k_pair<T, MIX, MODE, COMP, ROT>), dim3((unsigned)padded), dim3(64 * NW), 0, st, pos,         \
                      h->d_g_start.as<int32_t>(), h->d_g_cell0.as<int32_t>(), h->d_cell_start.as<int32_t>(), ev,    \
                      h->d_slot_base.as<int64_t>(), h->d_nl_off.as<int64_t>(), h->d_nl_e.as<int32_t>(),            \
-                     h->d_nl_d.as<int32_t>(), h->d_nl_r.as<int32_t>(), jpart, own, gpart, gnp, ng, padded, tab, at, \
-                     rot, evd, h->d_perm.as<int32_t>(), cap, pairs_out, pcount, h->epoch)
+                     h->d_nl_d.as<int32_t>(), h->d_nl_r.as<int32_t>(), jpart, own, gpart, gnp, ng, padded, tab,     \
+                     rot, evd, h->d_perm.as<int32_t>(), cap, pairs_out, pcount, mol_count, h->epoch)
 #define AICA_LAUNCH(MIX, COMP) AICA_LAUNCH_R(MIX, COMP, false)
   if (rot) {  // rotating referral: compensated sums always (the variants with a rotation are built once)
-    if constexpr (MODE == 2) {
-      if (nsp == 1) AICA_LAUNCH_R(0, true, true);
-      else AICA_LAUNCH_R(1, true, true);
-    } else {
-      if (nsp == 1) AICA_LAUNCH_R(0, true, true);
-      else if (nsp == 2) AICA_LAUNCH_R(1, true, true);
-      else AICA_LAUNCH_R(2, true, true);
-    }
-  } else if constexpr (MODE == 2) {  // the adjoint supports one or two species
-    if (nsp == 1) AICA_LAUNCH(0, true);
-    else AICA_LAUNCH(1, true);
-  } else if (MODE == 1) {
-    if (nsp == 1) AICA_LAUNCH(0, true);
-    else if (nsp == 2) AICA_LAUNCH(1, true);
-    else AICA_LAUNCH(2, true);
-  } else if (comp) {
+    if (nsp == 1) AICA_LAUNCH_R(0, true, true);
+    else if (nsp == 2) AICA_LAUNCH_R(1, true, true);
+    else AICA_LAUNCH_R(2, true, true);
+  } else if (MODE == 1 || comp) {
     if (nsp == 1) AICA_LAUNCH(0, true);
     else if (nsp == 2) AICA_LAUNCH(1, true);
     else AICA_LAUNCH(2, true);
@@ -1274,6 +1258,35 @@ static int launch_pair(aica_dil *h, const LJTab &tab, const AdjTab &at, bool com
   }
 #undef AICA_LAUNCH
 #undef AICA_LAUNCH_R
+  HIPCHK(hipGetLastError());
+  return AICA_OK;
+}
+
+// The adjoint pair kernel (one or two species).
+template <typename T>
+static int launch_adj(aica_dil *h, const LJTab &tab, const AdjTab &at, hipStream_t st) {
+  using V4 = typename Vec4<T>::type;
+  const int64_t ng = h->grp.ng;
+  constexpr int NW = adj_waves(sizeof(T));
+  const int64_t nblocks = (ng + NW - 1) / NW;
+  const int64_t padded = ((nblocks + 7) / 8) * 8;
+  const V4 *ev = sizeof(T) == 4 ? (const V4 *)h->d_e_vec32.p : (const V4 *)h->d_e_vec64.p;
+  const double *rot = h->geo.has_rot ? h->d_rot64.as<double>() : nullptr;
+  const double4 *evd = h->geo.has_rot ? h->d_e_vec64.as<double4>() : nullptr;
+#define AICA_LAUNCH_ADJ(MIX, ROT)                                                                                   \
+  hipLaunchKernelGGL((k_pair_adj<T, MIX, ROT>), dim3((unsigned)padded), dim3(64 * NW), 0, st, h->d_pos.as<V4>(),   \
+                     h->d_gG.as<V4>(), h->d_g_start.as<int32_t>(), h->d_g_cell0.as<int32_t>(),                     \
+                     h->d_cell_start.as<int32_t>(), ev, h->d_slot_base.as<int64_t>(), h->d_nl_off.as<int64_t>(),    \
+                     h->d_nl_e.as<int32_t>(), h->d_nl_d.as<int32_t>(), h->d_nl_r.as<int32_t>(), h->d_jpart.as<T>(), \
+                     h->d_own.as<T>(), h->d_gpar.as<double>(), ng, padded, tab, at, rot, evd, h->epoch)
+  if (rot) {
+    if (tab.nsp == 1) AICA_LAUNCH_ADJ(0, true);
+    else AICA_LAUNCH_ADJ(1, true);
+  } else {
+    if (tab.nsp == 1) AICA_LAUNCH_ADJ(0, false);
+    else AICA_LAUNCH_ADJ(1, false);
+  }
+#undef AICA_LAUNCH_ADJ
   HIPCHK(hipGetLastError());
   return AICA_OK;
 }
@@ -1324,9 +1337,7 @@ static int forces_impl(aica_dil *h, const void *pos_dev, const int32_t *species,
   if ((rc = h->d_red.ensure(sizeof(double) * 8 * kRedBlocks))) return rc;
   {
     ProfScope ps(h, "pair_fwd", st);
-    AdjTab at;
-    memset(&at, 0, sizeof at);
-    if ((rc = launch_pair<T, 0>(h, tab, at, comp, st, 0, nullptr))) return rc;
+    if ((rc = launch_pair<T, 0>(h, tab, comp, st, 0, nullptr))) return rc;
     h->wsteps_valid = true;
   }
   {
@@ -1376,14 +1387,12 @@ int aica_pairs_export(aica_dil *h, const void *pos_dev, const aica_params *param
   if ((rc = h->d_pcount.ensure(64))) return rc;
   unsigned long long *pc = h->d_pcount.as<unsigned long long>();
   hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, pc, (int64_t)1, 0ull);
-  AdjTab at;
-  memset(&at, 0, sizeof at);
   if (params->precision == AICA_FP32) {
     if ((rc = gather<float>(h, pos_dev, nullptr, 1, st))) return rc;
-    if ((rc = launch_pair<float, 1>(h, tab, at, false, st, cap, pc))) return rc;
+    if ((rc = launch_pair<float, 1>(h, tab, false, st, cap, pc))) return rc;
   } else {
     if ((rc = gather<double>(h, pos_dev, nullptr, 1, st))) return rc;
-    if ((rc = launch_pair<double, 1>(h, tab, at, false, st, cap, pc))) return rc;
+    if ((rc = launch_pair<double, 1>(h, tab, false, st, cap, pc))) return rc;
   }
   unsigned long long cnt = 0;
   HIPCHK(hipMemcpyAsync(&cnt, pc, 8, hipMemcpyDeviceToHost, st));
@@ -1416,6 +1425,27 @@ int aica_pairs_export(aica_dil *h, const void *pos_dev, const aica_params *param
 int aica_forces_adjoint(aica_dil *h, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
                         const void *grad_forces_dev, double grad_energy, void *grad_pos_dev, double *grad_eps_dev,
                         double *grad_sigma_dev, void *hip_stream);
+
+int aica_pair_counts(aica_dil *h, const void *pos_dev, const aica_params *params, int32_t *counts_dev,
+                     void *hip_stream) {
+  int rc = check_step(h, pos_dev);
+  if (rc) return rc;
+  if (h->n > 0 && !counts_dev) return fail(AICA_E_INVAL, "counts_dev is NULL");
+  LJTab tab;
+  if ((rc = build_tab(h, params, tab))) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (h->n == 0) return AICA_OK;
+  hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(h->n, 256)), dim3(256), 0, st, counts_dev, h->n, 0);
+  if (params->precision == AICA_FP32) {
+    if ((rc = gather<float>(h, pos_dev, nullptr, 1, st))) return rc;
+    if ((rc = launch_pair<float, 1>(h, tab, false, st, -1, nullptr, counts_dev))) return rc;
+  } else {
+    if ((rc = gather<double>(h, pos_dev, nullptr, 1, st))) return rc;
+    if ((rc = launch_pair<double, 1>(h, tab, false, st, -1, nullptr, counts_dev))) return rc;
+  }
+  HIPCHK(hipGetLastError());
+  return AICA_OK;
+}
 
 int aica_dil_export(const aica_dil *h, int64_t *n, int32_t *c, int32_t *d, int8_t *img) {
   if (!h || !n) return fail(AICA_E_INVAL, "NULL argument");
