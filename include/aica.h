@@ -121,11 +121,12 @@ int aica_build_dil_ex(const aica_mesh *mesh, double rcut, double guard, int32_t 
  * inside the ball kept from its last record test in its previous cell needs
  * no test at all; otherwise the previous cell is tested first, then the cells
  * across its faces, then a background grid.  The answer does not depend on
- * the history (every route certifies the same cell).  Synchronises the stream
- * once, to read the unlocated, over-occupied and reaction-slot counts.
- * Errors: AICA_E_INVAL (n < 0 or n >= 2^28 - 1, null, bad dtype, or a cell
- * holding more than 192 molecules), AICA_E_UNLOCATED (the count is in
- * aica_last_error), AICA_E_NOMEM (more than 2^31 reaction records), AICA_E_HIP. */
+ * the history (every route certifies the same cell).  A cell may hold any
+ * number of molecules.  Synchronises the stream once, to read the unlocated
+ * and reaction-slot counts.
+ * Errors: AICA_E_INVAL (n < 0 or n >= 2^28 - 1, null, bad dtype),
+ * AICA_E_UNLOCATED (the count is in aica_last_error), AICA_E_NOMEM (more than
+ * 2^31 reaction records), AICA_E_HIP. */
 int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, void *hip_stream);
 
 /* Per-step forces (Sec. 2.3.1 real-real and 2.3.2 real-referred loops, with
@@ -146,8 +147,8 @@ int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, v
  * decided exactly for positions that are multiples of 2^-15 (pairs within
  * 2^-20 rc^2 of rc^2 are decided in FP64), except for images with a rotation:
  * a rotated position is formed in FP64 and kept as an FP32 value plus its FP32
- * remainder, so only a pair within about 1e-7 rc^2 of rc^2 may be decided
- * either way (the adjoint uses the FP32 value alone).
+ * remainder (the adjoint forms the pair vector from both), so only a pair
+ * within about 1e-7 rc^2 of rc^2 may be decided either way.
  * Errors: AICA_E_INVAL, AICA_E_NOMEM, AICA_E_HIP. */
 int aica_forces(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
                 void *forces_dev, double *uw_dev, int64_t *npairs_dev, void *hip_stream);
@@ -160,10 +161,11 @@ int aica_forces(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, 
  * grad_energy: gamma (host scalar).  grad_pos_dev: device [n][3] compute dtype,
  * overwritten.  grad_eps_dev, grad_sigma_dev: device double[n_species],
  * overwritten (either may be NULL).  Same preconditions as aica_forces;
- * params->n_species must be 1 or 2.  Precision: with AICA_FP32 the pair terms
- * (which carry up to r^-16) are good to about 1e-6 of themselves, so a row whose
- * dL/dx is dominated by a contact closer than about 1 sigma can differ from the
- * exact value by more than 1e-5 of the rms of dL/dx; AICA_FP64 has no such limit.
+ * params->n_species must be 1 or 2.  Precision: the pair terms (which carry up
+ * to r^-16) are formed in FP64 in both precisions, from the FP32 positions and G
+ * with AICA_FP32 (whose differences are exact for multiples of 2^-15), and summed
+ * per molecule in FP64; with AICA_FP32 only the roundings of the per-entry
+ * partial sums and of the result to FP32 remain.
  * Errors: AICA_E_INVAL (also for more than two species), AICA_E_NOMEM, AICA_E_HIP. */
 int aica_forces_adjoint(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
                         const void *grad_forces_dev, double grad_energy, void *grad_pos_dev, double *grad_eps_dev,
@@ -183,6 +185,14 @@ int aica_dil_export(const aica_dil *dil, int64_t *n, int32_t *c, int32_t *d, int
  * count (which may exceed cap: call again with a larger cap). */
 int aica_pairs_export(aica_dil *dil, const void *pos_dev, const aica_params *params, int64_t cap, int64_t *n,
                       int32_t *a, int32_t *b, int8_t *img, void *hip_stream);
+
+/* Per-molecule pair counts: counts_dev[a] = the number of pairs inside the cut-off that molecule a takes
+ * part in (each pair counts for both molecules; a molecule paired with its own image counts twice), from
+ * the same traversal as aica_forces after aica_bin.  counts_dev: device int32 [n], caller order,
+ * overwritten.  params: rcut and precision are used (the cut-off is decided as aica_forces decides it).
+ * Same preconditions as aica_forces.  Errors: AICA_E_INVAL, AICA_E_NOMEM, AICA_E_HIP. */
+int aica_pair_counts(aica_dil *dil, const void *pos_dev, const aica_params *params, int32_t *counts_dev,
+                     void *hip_stream);
 
 /* Binning of the last aica_bin, host arrays: cell_of[n] (mesh cell id of each
  * molecule), order[n] (molecule ids in cell-sorted order), cell_count[n_cells]

@@ -16,6 +16,7 @@ from ._lib import (AICA_E_INVAL, AICA_E_MESH, AICA_E_RCUT, AICA_E_UNLOCATED, AIC
                    aica_info, aica_mesh, aica_params, check, lib)
 
 __all__ = ["DIL", "aica_build_dil", "aica_bin", "aica_forces", "aica_forces_adjoint", "aica_pairs_export",
+           "aica_pair_counts",
            "aica_dil_export", "aica_bin_export", "AicaLJ", "AicaError", "AICA_FP32", "AICA_FP64",
            "AICA_E_INVAL", "AICA_E_MESH", "AICA_E_RCUT", "AICA_E_UNLOCATED"]
 
@@ -201,6 +202,18 @@ def aica_pairs_export(dil: DIL, pos, rcut=None, precision="fp32"):
     k = n.value
     key = np.stack([a[:k], b[:k], im[:k, 0], im[:k, 1], im[:k, 2]], axis=1).astype(np.int64)
     return key[np.lexsort(key.T[::-1])]
+
+
+def aica_pair_counts(dil: DIL, pos, rcut=None, precision="fp32"):
+    """Pairs inside the cut-off per molecule ([n] int32 on the device, caller order), from the traversal of
+    aica_forces."""
+    import torch
+    _check_pos(pos)
+    p, keep = _params(dil.rcut if rcut is None else rcut, (1.0,), (1.0,), precision, False)
+    counts = torch.empty(pos.shape[0], dtype=torch.int32, device=pos.device)
+    check(lib().aica_pair_counts(dil.h, C.c_void_p(pos.data_ptr()), C.byref(p), C.c_void_p(counts.data_ptr()),
+                                 _stream(pos)))
+    return counts
 
 
 def aica_dil_export(dil: DIL):

@@ -25,9 +25,10 @@ ERROR_NAMES = {AICA_E_INVAL: "AICA_E_INVAL", AICA_E_MESH: "AICA_E_MESH", AICA_E_
 AICA_DIL_CLOSEST = 0
 AICA_DIL_VERTEX = 1
 
-EXPORTED = ["aica_build_dil", "aica_build_dil_ex", "aica_bin", "aica_forces", "aica_forces_adjoint", "aica_dil_export",
-            "aica_pairs_export", "aica_bin_export", "aica_dil_info", "aica_work_stats", "aica_profile", "aica_profile_read",
-            "aica_last_error", "aica_dil_free"]
+EXPORTED = ["aica_build_dil", "aica_build_dil_ex", "aica_bin", "aica_forces", "aica_forces_adjoint",
+            "aica_dil_export", "aica_pairs_export", "aica_pair_counts", "aica_bin_export",
+            "aica_dil_info", "aica_work_stats", "aica_profile", "aica_profile_read", "aica_last_error",
+            "aica_dil_free"]
 
 
 class AicaError(RuntimeError):
@@ -75,6 +76,7 @@ def lib():
         L.aica_forces_adjoint.argtypes = [p, p, p, C.POINTER(aica_params), p, f64, p, p, p, p]
         L.aica_dil_export.argtypes = [p, p, p, p, p]
         L.aica_pairs_export.argtypes = [p, p, C.POINTER(aica_params), i64, p, p, p, p, p]
+        L.aica_pair_counts.argtypes = [p, p, C.POINTER(aica_params), p, p]
         L.aica_bin_export.argtypes = [p, p, p, p]
         L.aica_dil_info.argtypes = [p, C.POINTER(aica_info)]
         L.aica_work_stats.argtypes = [p, p, p]

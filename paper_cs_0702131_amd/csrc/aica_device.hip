@@ -1200,12 +1200,20 @@ static int build_tab(const aica_dil *h, const aica_params *p, LJTab &t) {
   return AICA_OK;
 }
 
+// Device buffers of one force call (the handle's grow-only workspace).  pos: [n] gathered positions;
+// own: [2n] (hi, lo) own records; jpart: [J] reaction records tagged with epoch; gpart, gnp: per-group
+// partials; red: stage-1 reduction rows.
+struct ForceWs {
+  void *pos = nullptr, *own = nullptr, *jpart = nullptr, *gpart = nullptr, *gnp = nullptr, *red = nullptr;
+  uint32_t epoch = 0;
+};
+
 // Reaction buffer: (re)allocate, fill with a pattern no epoch can equal, and advance the epoch.
 static int prepare_jpart(aica_dil *h, size_t bytes, hipStream_t st) {
   const void *old = h->d_jpart.p;
   int rc = h->d_jpart.ensure(bytes);
   if (rc) return rc;
-  if (h->d_jpart.p != old || h->jpart_tagged < h->d_jpart.bytes || h->epoch >= 0x7FFFFFF0u) {
+  if (h->d_jpart.p != old || h->jpart_tagged < h->d_jpart.bytes || h->epoch >= kMaxEpoch) {
     const int64_t words = (int64_t)(h->d_jpart.bytes / 4);
     hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid1d(words, 256)), dim3(256), 0, st, h->d_jpart.as<uint32_t>(),
                        words, 0xFFFFFFFFu);
@@ -1218,19 +1226,19 @@ static int prepare_jpart(aica_dil *h, size_t bytes, hipStream_t st) {
 }
 
 template <typename T, int MODE>
-static int launch_pair(aica_dil *h, const LJTab &tab, bool comp, hipStream_t st, int64_t cap,
+static int launch_pair(aica_dil *h, const ForceWs &ws, const LJTab &tab, bool comp, hipStream_t st, int64_t cap,
                        unsigned long long *pcount, int32_t *mol_count = nullptr) {
   using V4 = typename Vec4<T>::type;
   const int64_t ng = h->grp.ng;
   constexpr int NW = pair_waves(sizeof(T));
   const int64_t nblocks = (ng + NW - 1) / NW;
   const int64_t padded = ((nblocks + 7) / 8) * 8;
-  const V4 *pos = h->d_pos.as<V4>();
+  const V4 *pos = (const V4 *)ws.pos;
   const V4 *ev = sizeof(T) == 4 ? (const V4 *)h->d_e_vec32.p : (const V4 *)h->d_e_vec64.p;
-  T *jpart = MODE == 1 ? nullptr : h->d_jpart.as<T>();
-  T *own = MODE == 1 ? nullptr : h->d_own.as<T>();
-  double *gpart = MODE == 0 ? h->d_gpart.as<double>() : nullptr;
-  unsigned long long *gnp = MODE == 0 ? h->d_gnp.as<unsigned long long>() : nullptr;
+  T *jpart = MODE == 1 ? nullptr : (T *)ws.jpart;
+  T *own = MODE == 1 ? nullptr : (T *)ws.own;
+  double *gpart = MODE == 0 ? (double *)ws.gpart : nullptr;
+  unsigned long long *gnp = MODE == 0 ? (unsigned long long *)ws.gnp : nullptr;
   int32_t *pairs_out = (MODE == 1 && cap >= 0) ? h->d_pairs.as<int32_t>() : nullptr;  // cap < 0: counts only
   // rotating referral: FP64 rotations and offsets for both precisions (the referred position is rounded once)
   const double *rot = h->geo.has_rot ? h->d_rot64.as<double>() : nullptr;
@@ -1241,7 +1249,7 @@ static int launch_pair(aica_dil *h, const LJTab &tab, bool comp, hipStream_t st,
                      h->d_g_start.as<int32_t>(), h->d_g_cell0.as<int32_t>(), h->d_cell_start.as<int32_t>(), ev,    \
                      h->d_slot_base.as<int64_t>(), h->d_nl_off.as<int64_t>(), h->d_nl_e.as<int32_t>(),            \
                      h->d_nl_d.as<int32_t>(), h->d_nl_r.as<int32_t>(), jpart, own, gpart, gnp, ng, padded, tab,     \
-                     rot, evd, h->d_perm.as<int32_t>(), cap, pairs_out, pcount, mol_count, h->epoch)
+                     rot, evd, h->d_perm.as<int32_t>(), cap, pairs_out, pcount, mol_count, ws.epoch)
 #define AICA_LAUNCH(MIX, COMP) AICA_LAUNCH_R(MIX, COMP, false)
   if (rot) {  // rotating referral: compensated sums always (the variants with a rotation are built once)
     if (nsp == 1) AICA_LAUNCH_R(0, true, true);
@@ -1277,7 +1285,7 @@ static int launch_adj(aica_dil *h, const LJTab &tab, const AdjTab &at, hipStream
   hipLaunchKernelGGL((k_pair_adj<T, MIX, ROT>), dim3((unsigned)padded), dim3(64 * NW), 0, st, h->d_pos.as<V4>(),   \
                      h->d_gG.as<V4>(), h->d_g_start.as<int32_t>(), h->d_g_cell0.as<int32_t>(),                     \
                      h->d_cell_start.as<int32_t>(), ev, h->d_slot_base.as<int64_t>(), h->d_nl_off.as<int64_t>(),    \
-                     h->d_nl_e.as<int32_t>(), h->d_nl_d.as<int32_t>(), h->d_nl_r.as<int32_t>(), h->d_jpart.as<T>(), \
+                     h->d_nl_e.as<int32_t>(), h->d_nl_d.as<int32_t>(), h->d_nl_r.as<int32_t>(), h->d_jpart.as<double>(), \
                      h->d_own.as<T>(), h->d_gpar.as<double>(), ng, padded, tab, at, rot, evd, h->epoch)
   if (rot) {
     if (tab.nsp == 1) AICA_LAUNCH_ADJ(0, true);
@@ -1292,28 +1300,56 @@ static int launch_adj(aica_dil *h, const LJTab &tab, const AdjTab &at, hipStream
 }
 
 template <typename T, bool COMP>
-static void launch_finalize(aica_dil *h, void *out, hipStream_t st) {
+static void launch_finalize(aica_dil *h, const ForceWs &ws, void *out, hipStream_t st) {
   const int64_t n = h->n;
-  hipLaunchKernelGGL((k_finalize<T, COMP>), dim3(grid1d(n, 256)), dim3(256), 0, st, h->d_own.as<T>(),
-                     h->d_jpart.as<T>(), h->jtotal, n, h->d_cell_sorted.as<int32_t>(), h->d_cell_start.as<int32_t>(),
+  hipLaunchKernelGGL((k_finalize<T, COMP>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const T *)ws.own,
+                     (const T *)ws.jpart, h->jtotal, n, h->d_cell_sorted.as<int32_t>(), h->d_cell_start.as<int32_t>(),
                      h->d_slot_base.as<int64_t>(), h->d_rcnt.as<int32_t>(), h->d_perm.as<int32_t>(), (T *)out,
-                     h->epoch);
+                     ws.epoch);
 }
 
+// Gather the binned positions into cell-sorted SoA at dst ([n] V4 of the compute type).
 template <typename T>
-static int gather(aica_dil *h, const void *pos_dev, const int32_t *species, int tab_nsp, hipStream_t st) {
+static int gather_to(aica_dil *h, const void *pos_dev, const int32_t *species, int tab_nsp, hipStream_t st, void *dst) {
   using V4 = typename Vec4<T>::type;
   const int64_t n = h->n;
-  int rc = h->d_pos.ensure(sizeof(V4) * std::max<int64_t>(n, 1));
-  if (rc) return rc;
   if (n == 0) return AICA_OK;
   if (h->bin_dtype == AICA_FP64)
     hipLaunchKernelGGL((k_gather<T, double>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const double *)pos_dev, species,
-                       h->d_perm.as<int32_t>(), h->d_mol_group.as<int32_t>(), h->d_orig.as<double>(), n, tab_nsp, h->d_pos.as<V4>());
+                       h->d_perm.as<int32_t>(), h->d_mol_group.as<int32_t>(), h->d_orig.as<double>(), n, tab_nsp, (V4 *)dst);
   else
     hipLaunchKernelGGL((k_gather<T, float>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const float *)pos_dev, species,
-                       h->d_perm.as<int32_t>(), h->d_mol_group.as<int32_t>(), h->d_orig.as<double>(), n, tab_nsp, h->d_pos.as<V4>());
+                       h->d_perm.as<int32_t>(), h->d_mol_group.as<int32_t>(), h->d_orig.as<double>(), n, tab_nsp, (V4 *)dst);
   HIPCHK(hipGetLastError());
+  return AICA_OK;
+}
+
+// Gather into the handle's own position buffer (grown as needed).
+template <typename T>
+static int gather(aica_dil *h, const void *pos_dev, const int32_t *species, int tab_nsp, hipStream_t st) {
+  using V4 = typename Vec4<T>::type;
+  int rc = h->d_pos.ensure(sizeof(V4) * std::max<int64_t>(h->n, 1));
+  if (rc) return rc;
+  return gather_to<T>(h, pos_dev, species, tab_nsp, st, h->d_pos.p);
+}
+
+// The handle's grow-only workspace for a force call (allocating on first use or growth).
+template <typename T>
+static int handle_ws(aica_dil *h, ForceWs &ws, hipStream_t st) {
+  const int64_t n = h->n, ng = h->grp.ng, J = h->jtotal;
+  int rc;
+  if ((rc = prepare_jpart(h, sizeof(T) * 4 * std::max<int64_t>(J, 1), st))) return rc;
+  if ((rc = h->d_own.ensure(sizeof(T) * 8 * std::max<int64_t>(n, 1)))) return rc;
+  if ((rc = h->d_gpart.ensure(sizeof(double) * 2 * std::max<int64_t>(ng, 1)))) return rc;
+  if ((rc = h->d_gnp.ensure(16 * std::max<int64_t>(ng, 1)))) return rc;
+  if ((rc = h->d_red.ensure(sizeof(double) * 8 * kRedBlocks))) return rc;
+  ws.pos = h->d_pos.p;
+  ws.own = h->d_own.p;
+  ws.jpart = h->d_jpart.p;
+  ws.gpart = h->d_gpart.p;
+  ws.gnp = h->d_gnp.p;
+  ws.red = h->d_red.p;
+  ws.epoch = h->epoch;
   return AICA_OK;
 }
 
@@ -1324,43 +1360,55 @@ static int check_step(aica_dil *h, const void *pos_dev) {
   return AICA_OK;
 }
 
+// Pair kernel, finalize and reductions of a force call on the workspace ws (positions already gathered).
 template <typename T>
-static int forces_impl(aica_dil *h, const void *pos_dev, const int32_t *species, const LJTab &tab, bool comp,
-                       void *forces_dev, double *uw_dev, int64_t *npairs_dev, hipStream_t st) {
-  const int64_t n = h->n, ng = h->grp.ng, J = h->jtotal;
+static int forces_impl(aica_dil *h, const ForceWs &ws, const LJTab &tab, bool comp, void *forces_dev, double *uw_dev,
+                       int64_t *npairs_dev, hipStream_t st, bool prof = true) {
+  const int64_t n = h->n, ng = h->grp.ng;
   int rc;
-  if ((rc = gather<T>(h, pos_dev, species, tab.nsp, st))) return rc;
-  if ((rc = prepare_jpart(h, sizeof(T) * 4 * std::max<int64_t>(J, 1), st))) return rc;
-  if ((rc = h->d_own.ensure(sizeof(T) * 8 * std::max<int64_t>(n, 1)))) return rc;
-  if ((rc = h->d_gpart.ensure(sizeof(double) * 2 * std::max<int64_t>(ng, 1)))) return rc;
-  if ((rc = h->d_gnp.ensure(16 * std::max<int64_t>(ng, 1)))) return rc;
-  if ((rc = h->d_red.ensure(sizeof(double) * 8 * kRedBlocks))) return rc;
+  const bool was = h->profiling;
+  h->profiling = was && prof;  // the timing events are created only where the call may allocate
+  struct Restore {
+    aica_dil *h;
+    bool v;
+    ~Restore() { h->profiling = v; }
+  } restore{h, was};
   {
     ProfScope ps(h, "pair_fwd", st);
-    if ((rc = launch_pair<T, 0>(h, tab, comp, st, 0, nullptr))) return rc;
-    h->wsteps_valid = true;
+    if ((rc = launch_pair<T, 0>(h, ws, tab, comp, st, 0, nullptr))) return rc;
+    h->wsteps_valid = ws.gnp == h->d_gnp.p;  // the lane-pair diagnostic reads the handle's partials
   }
   {
     ProfScope ps(h, "finalize", st);
     if (n > 0 && forces_dev) {
       if (comp && sizeof(T) == 4)
-        launch_finalize<T, true>(h, forces_dev, st);
+        launch_finalize<T, true>(h, ws, forces_dev, st);
       else
-        launch_finalize<T, false>(h, forces_dev, st);
+        launch_finalize<T, false>(h, ws, forces_dev, st);
     }
     if (uw_dev || npairs_dev) {
       int64_t chunk;
       const int nb = red_blocks(ng, chunk);
-      double *pu = h->d_red.as<double>(), *pn = pu + 2 * kRedBlocks;
-      hipLaunchKernelGGL((k_reduce_rows<2, double>), dim3(nb), dim3(kRedThreads), 0, st, h->d_gpart.as<double>(), ng,
+      double *pu = (double *)ws.red, *pn = pu + 2 * kRedBlocks;
+      hipLaunchKernelGGL((k_reduce_rows<2, double>), dim3(nb), dim3(kRedThreads), 0, st, (const double *)ws.gpart, ng,
                          2, 0, chunk, pu);
       hipLaunchKernelGGL((k_reduce_rows<1, unsigned long long>), dim3(nb), dim3(kRedThreads), 0, st,
-                         h->d_gnp.as<unsigned long long>(), ng, 2, 0, chunk, pn);
+                         (const unsigned long long *)ws.gnp, ng, 2, 0, chunk, pn);
       hipLaunchKernelGGL(k_reduce_uw, dim3(1), dim3(kRedThreads), 0, st, pu, pn, nb, uw_dev, npairs_dev);
     }
     HIPCHK(hipGetLastError());
   }
   return AICA_OK;
+}
+
+template <typename T>
+static int forces_alloc(aica_dil *h, const void *pos_dev, const int32_t *species, const LJTab &tab, bool comp,
+                        void *forces_dev, double *uw_dev, int64_t *npairs_dev, hipStream_t st) {
+  int rc;
+  if ((rc = gather<T>(h, pos_dev, species, tab.nsp, st))) return rc;
+  ForceWs ws;
+  if ((rc = handle_ws<T>(h, ws, st))) return rc;
+  return forces_impl<T>(h, ws, tab, comp, forces_dev, uw_dev, npairs_dev, st);
 }
 
 int aica_forces(aica_dil *h, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
@@ -1371,8 +1419,8 @@ int aica_forces(aica_dil *h, const void *pos_dev, const int32_t *species_dev, co
   if ((rc = build_tab(h, params, tab))) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
   if (params->precision == AICA_FP32)
-    return forces_impl<float>(h, pos_dev, species_dev, tab, params->compensated != 0, forces_dev, uw_dev, npairs_dev, st);
-  return forces_impl<double>(h, pos_dev, species_dev, tab, false, forces_dev, uw_dev, npairs_dev, st);
+    return forces_alloc<float>(h, pos_dev, species_dev, tab, params->compensated != 0, forces_dev, uw_dev, npairs_dev, st);
+  return forces_alloc<double>(h, pos_dev, species_dev, tab, false, forces_dev, uw_dev, npairs_dev, st);
 }
 
 int aica_pairs_export(aica_dil *h, const void *pos_dev, const aica_params *params, int64_t cap, int64_t *n_out,
@@ -1389,10 +1437,14 @@ int aica_pairs_export(aica_dil *h, const void *pos_dev, const aica_params *param
   hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(64), 0, st, pc, (int64_t)1, 0ull);
   if (params->precision == AICA_FP32) {
     if ((rc = gather<float>(h, pos_dev, nullptr, 1, st))) return rc;
-    if ((rc = launch_pair<float, 1>(h, tab, false, st, cap, pc))) return rc;
+    ForceWs ws;
+    ws.pos = h->d_pos.p;
+    if ((rc = launch_pair<float, 1>(h, ws, tab, false, st, cap, pc))) return rc;
   } else {
     if ((rc = gather<double>(h, pos_dev, nullptr, 1, st))) return rc;
-    if ((rc = launch_pair<double, 1>(h, tab, false, st, cap, pc))) return rc;
+    ForceWs ws;
+    ws.pos = h->d_pos.p;
+    if ((rc = launch_pair<double, 1>(h, ws, tab, false, st, cap, pc))) return rc;
   }
   unsigned long long cnt = 0;
   HIPCHK(hipMemcpyAsync(&cnt, pc, 8, hipMemcpyDeviceToHost, st));
@@ -1438,10 +1490,14 @@ int aica_pair_counts(aica_dil *h, const void *pos_dev, const aica_params *params
   hipLaunchKernelGGL((k_fill<int32_t>), dim3(grid1d(h->n, 256)), dim3(256), 0, st, counts_dev, h->n, 0);
   if (params->precision == AICA_FP32) {
     if ((rc = gather<float>(h, pos_dev, nullptr, 1, st))) return rc;
-    if ((rc = launch_pair<float, 1>(h, tab, false, st, -1, nullptr, counts_dev))) return rc;
+    ForceWs ws;
+    ws.pos = h->d_pos.p;
+    if ((rc = launch_pair<float, 1>(h, ws, tab, false, st, -1, nullptr, counts_dev))) return rc;
   } else {
     if ((rc = gather<double>(h, pos_dev, nullptr, 1, st))) return rc;
-    if ((rc = launch_pair<double, 1>(h, tab, false, st, -1, nullptr, counts_dev))) return rc;
+    ForceWs ws;
+    ws.pos = h->d_pos.p;
+    if ((rc = launch_pair<double, 1>(h, ws, tab, false, st, -1, nullptr, counts_dev))) return rc;
   }
   HIPCHK(hipGetLastError());
   return AICA_OK;

@@ -1,5 +1,7 @@
 """GPU parity of the hand-written adjoint: against the oracle's analytic gradient,
-FP64 central finite differences, torch.autograd.gradcheck, and identities."""
+FP64 central finite differences, torch.autograd.gradcheck, and identities.  Bars: FP64 1e-12; FP32
+1e-6 (the pair terms are formed and summed per molecule in FP64 in both precisions, so only the
+roundings of the partial sums and of the result to FP32 remain)."""
 import sys
 
 import numpy as np
@@ -55,7 +57,7 @@ def test_adjoint_vs_oracle(A, oracle, frac):
     wl, G = _case(frac=frac)
     gam = 0.1
     rx, re, rs, rL = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
-    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
         gx, ge, gs, L = gpu_adjoint(A, wl, G, gam, prec)
         ex = rel_max(gx, rx)
         ee = np.abs(ge - re).max() / np.abs(re).max()
@@ -71,7 +73,7 @@ def test_adjoint_vs_finite_differences(A, oracle):
     wl, G = _case(seed=41, N=200)
     gam = 0.1
     h = 1e-6
-    for prec, tol in (("fp64", 1e-6), ("fp32", 1e-5)):
+    for prec, tol in (("fp64", 1e-6), ("fp32", 1e-6)):
         gx, ge, gs, _ = gpu_adjoint(A, wl, G, gam, prec)
         for which, grad in (("eps", ge), ("sigma", gs)):
             for p in range(len(wl.eps)):
@@ -124,7 +126,7 @@ def test_full_size_identities(A):
     wl = W.config4()
     G = wl.extra["G"]
     d = A.DIL(wl.mesh, wl.rcut)
-    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-6)):
         gx, ge, gs, L = gpu_adjoint(A, wl, G, wl.extra["gamma"], prec, dil=d)
         _note(f"config4 adjoint {prec}: sum dL/dx {np.abs(gx.sum(0)).max():.3e}, "
               f"eps-homogeneity {abs((wl.eps * ge).sum() - L) / abs(L):.3e}")
@@ -145,7 +147,7 @@ def test_one_species_with_scaled_parameters(A, oracle):
     Fr, Ur, Wr, nr = oracle.forces(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic)
     rx, re, rs, rL = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
     d = A.DIL(wl.mesh, wl.rcut)
-    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-5)):
+    for prec, dt, tol, tolA in (("fp64", torch.float64, 1e-12, 1e-12), ("fp32", torch.float32, 1e-5, 1e-6)):
         x = torch.tensor(wl.x, dtype=dt, device="cuda")
         A.aica_bin(d, x)
         F, uw, npairs = A.aica_forces(d, x, None, wl.eps, wl.sigma, precision=prec)
@@ -160,5 +162,5 @@ def test_one_species_with_scaled_parameters(A, oracle):
         _note(f"eps 0.7 sigma 1.3 {prec}: e_F {eF:.2e} dU {abs(uw[0].item() - Ur) / abs(Ur):.2e} "
               f"dx {ex:.2e} deps {ee:.2e} dsig {es:.2e}")
         assert int(npairs.cpu()[0]) == nr
-        assert eF < tol and ex < tol and ee < tol and es < tol
+        assert eF < tol and ex < tolA and ee < tolA and es < tolA
         assert abs(uw[0].item() - Ur) <= tol * abs(Ur) and abs(uw[1].item() - Wr) <= tol * abs(Wr)

@@ -90,6 +90,21 @@ def test_small_random_both_precisions(A, oracle, seed, periodic, species):
     check_case(A, oracle, wl, "fp32", 1e-5, 1e-6)
 
 
+@pytest.mark.parametrize("seed,periodic", [(5, (0, 1, 2)), (6, (1,))])
+def test_pair_counts_per_molecule(A, oracle, seed, periodic):
+    """aica_pair_counts against the oracle's pair list: every pair counts once for each member, a molecule
+    paired with its own image twice; both precisions, caller order."""
+    wl = W.small_random(n_mesh=(4, 3, 5), L=(8.5, 7.0, 9.0), N=300, periodic_axes=periodic, seed=seed,
+                        species_frac=0.5)
+    P = oracle.pairs(wl.x, wl.rcut, wl.mesh.periodic)
+    ref = np.bincount(P[:, 0], minlength=wl.n) + np.bincount(P[:, 1], minlength=wl.n)
+    for prec in ("fp64", "fp32"):
+        d, x, _, _, npairs = run_gpu(A, wl, prec)
+        counts = A.aica_pair_counts(d, x, precision=prec).cpu().numpy()
+        assert np.array_equal(counts, ref), prec
+        assert npairs == len(P)
+
+
 def test_cutoff_band_pairs(A, oracle):
     # separations within a few FP32 ulps of rc^2 on both sides (and exactly rc): the FP32 path must
     # reproduce the exact pair set, including pairs where a plain FP32 evaluation of s decides wrongly
@@ -114,6 +129,44 @@ def test_dense_coarse_mesh_many_chunks(A, oracle):
     wl = W.small_random(n_mesh=(2, 2, 2), L=(8.4, 8.4, 8.4), N=470, seed=8, min_sep=0.85, species_frac=0.8)
     check_case(A, oracle, wl, "fp64", 1e-12, 1e-12)
     check_case(A, oracle, wl, "fp32", 1e-5, 1e-6)
+
+
+@pytest.mark.parametrize("L,n_fcc,frac", [(13.44, 8, None), (18.48, 11, 0.6)])
+def test_cells_beyond_a_segment(A, oracle, L, n_fcc, frac):
+    """A 2x2x2 periodic mesh of cells holding 256 or 665-666 molecules each (an FCC fluid at density 0.845):
+    every cell is larger than a j segment in both precisions (at most 240 expanded j), so neighbour cells
+    are split across segments and groups need four to eleven passes.  Forces, U, W, the pair set, the
+    per-molecule pair counts and the adjoint against the oracle in both precisions."""
+    import torch
+    wl = W.fcc_cube(L, 2, n_fcc, jitter=0.05, seed=int(10 * L), name=f"fcc{4 * n_fcc ** 3}_mesh2")
+    if frac is not None:
+        rng = np.random.default_rng(int(10 * L) + 1)
+        wl.species = (rng.random(wl.n) < frac).astype(np.int32)
+        wl.eps, wl.sigma = np.array([1.0, 0.7]), np.array([1.0, 0.9])
+    d0 = A.DIL(wl.mesh, wl.rcut)
+    A.aica_bin(d0, torch.tensor(wl.x, dtype=torch.float64, device="cuda"))
+    _, _, count = A.aica_bin_export(d0, wl.n)
+    assert count.sum() == wl.n and count.min() >= wl.n // 8 > 240
+    check_case(A, oracle, wl, "fp64", 1e-12, 1e-12)
+    check_case(A, oracle, wl, "fp32", 1e-5, 1e-6)
+    P = oracle.pairs(wl.x, wl.rcut, wl.mesh.periodic)
+    ref = np.bincount(P[:, 0], minlength=wl.n) + np.bincount(P[:, 1], minlength=wl.n)
+    G = W.qround(np.random.default_rng(int(10 * L) + 2).standard_normal((wl.n, 3)))
+    rx, re, rs, _ = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, 0.1)
+    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-6)):
+        xt = torch.tensor(wl.x, dtype=dt, device="cuda")
+        sp = torch.tensor(wl.species, dtype=torch.int32, device="cuda")
+        A.aica_bin(d0, xt)
+        counts = A.aica_pair_counts(d0, xt, precision=prec).cpu().numpy()
+        assert np.array_equal(counts, ref), prec
+        gx, ge, gs = A.aica_forces_adjoint(d0, xt, torch.tensor(G, dtype=dt, device="cuda"), 0.1, sp, wl.eps,
+                                           wl.sigma, precision=prec)
+        gx = gx.double().cpu().numpy()
+        ex = np.abs(gx - rx).max() / np.sqrt((rx ** 2).mean())
+        ee = np.abs(ge.cpu().numpy() - re).max() / np.abs(re).max()
+        es = np.abs(gs.cpu().numpy() - rs).max() / np.abs(rs).max()
+        _note(f"  {wl.name} adjoint {prec}: dx {ex:.2e} deps {ee:.2e} dsig {es:.2e}")
+        assert ex < tol and ee < tol and es < tol, prec
 
 
 def test_edge_cases_tiny(A, oracle):
@@ -216,8 +269,8 @@ def test_config2_walls_jittered(A, oracle):
 
 def test_config4_full_size_sampled_rows(A, oracle):
     """219,488-molecule binary mixture at full size: the FP32 and FP64 forces on 600 sampled
-    rows against the oracle (each row summed over all molecules), exact pair counts per row via
-    the total, and zero net force."""
+    rows against the oracle (each row summed over all molecules), exact pair counts on those rows,
+    and zero net force."""
     wl = W.config4()
     rows = np.random.default_rng(40).choice(wl.n, 600, replace=False)
     Fr, Ur, Wr, cnt = oracle.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, rows)
@@ -229,6 +282,9 @@ def test_config4_full_size_sampled_rows(A, oracle):
         _note(f"config4 {prec} sampled e_F = {err:.3e}, npairs = {npairs}")
         assert err < tol, err
         assert abs(F.sum(0)).max() < (1e-9 if prec == "fp64" else 1e-2) * np.abs(F).sum(0).max()
+        counts = A.aica_pair_counts(d, x, precision=prec).cpu().numpy()
+        assert np.array_equal(counts[rows], cnt), prec
+        assert int(counts.sum()) == 2 * npairs
 
 
 def test_binning_tracking_after_moves(A, oracle):
@@ -341,10 +397,10 @@ def test_binning_balls_and_routes(A, oracle):
 
 
 def test_cells_at_the_occupancy_limit(A, oracle):
-    """Eight cells of 190 molecules each (the limit is 192): in the FP64 forward (segments of 192) a
-    neighbour cell never fits beside the j carried over from the previous segment, so segment
-    boundaries take the path that first evaluates the carried j on their own; groups hold one cell,
-    i.e. three passes of up to 64."""
+    """Eight cells of 190 molecules each: in the FP64 forward (segments of 192 expanded j) a neighbour
+    cell never fits beside the j carried over from the previous segment, so segment boundaries take the
+    path that first evaluates the carried j on their own, and neighbour cells are split across segments;
+    groups hold one cell, i.e. three passes of up to 64."""
     import torch
     L, per = 14.0, 190
     sites = []
@@ -371,7 +427,7 @@ def test_cells_at_the_occupancy_limit(A, oracle):
     check_case(A, oracle, wl, "fp32", 1e-5, 2e-5)
     G = W.qround(np.random.default_rng(63).standard_normal((n, 3)))
     rx, _, _, _ = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, 0.1)
-    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-5)):
+    for prec, dt, tol in (("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 1e-6)):
         xt = torch.tensor(wl.x, dtype=dt, device="cuda")
         A.aica_bin(d, xt)
         gx, _, _ = A.aica_forces_adjoint(d, xt, torch.tensor(G, dtype=dt, device="cuda"), 0.1, None, wl.eps,

@@ -4,7 +4,8 @@ sides are coupled by the rotation about z, periodic in z.
 Checks: forces, energy, virial, pair count and pair set against the FP64 oracle; the adjoint against
 the oracle; the binning against brute-force location; the GPU sector against the GPU whole annulus
 (rotated copies, z translation only); the torque about the axis and the axial force, which vanish
-for any rotationally periodic system.  Bars as for translations: FP64 1e-12, FP32 1e-5."""
+for any rotationally periodic system.  Bars as for translations: FP64 1e-12; FP32 1e-5 for the forces
+and 1e-6 for the adjoint."""
 import sys
 
 import numpy as np
@@ -182,7 +183,7 @@ def test_wedge_adjoint_vs_oracle(A, oracle):
     gam = 0.2
     rx, re, rs, rL = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.lattice, G, gam,
                                     rot=wl.rotations)
-    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
         d = A.DIL(wl.mesh, wl.rcut)
         dt = torch.float64 if prec == "fp64" else torch.float32
         x = torch.tensor(wl.x, dtype=dt, device="cuda")
