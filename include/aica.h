@@ -153,6 +153,26 @@ int aica_bin(aica_dil *dil, const void *pos_dev, int32_t pos_dtype, int64_t n, v
 int aica_forces(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
                 void *forces_dev, double *uw_dev, int64_t *npairs_dev, void *hip_stream);
 
+/* aica_forces for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments, preconditions and results (bit for bit) as aica_forces, but every
+ * buffer of the call lies in a fixed device array of 128 MiB that the library
+ * holds on each GPU it runs on until the process ends; the call allocates and
+ * frees nothing.  The array holds the cell-sorted positions (16 or 32 bytes per
+ * molecule), the own records (32 or 64 bytes per molecule), the reaction records
+ * (16 or 32 bytes each, aica_info.n_jslots of them) and per-group partials
+ * (32 bytes per group), each region rounded up to 256 bytes, plus 32 KiB; a step
+ * that needs more fails with AICA_E_INVAL (the message names the bytes needed)
+ * and nothing is launched.  The handle and its binning (aica_build_dil, aica_bin)
+ * are prepared beforehand by those calls, which may allocate.  The array keeps
+ * the last call's contents; each call first clears the reaction records' tags
+ * (a fill kernel, no memset).  All calls on one GPU share the array: calls that
+ * overlap in time on one GPU (other streams, other threads, other handles) race
+ * and give wrong results; order them on one stream.  aica_profile timing is not
+ * recorded for this call.  Errors: AICA_E_INVAL, AICA_E_HIP. */
+int aica_forces_noalloc(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
+                        void *forces_dev, double *uw_dev, int64_t *npairs_dev, void *hip_stream);
+
 /* Adjoint of the force evaluation for L = sum_a G_a . F_a + gamma U (the
  * upstream gradient G on the forces and gamma on the energy).  Recomputes
  * every pair term (nothing is stored between the calls):

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import (AICA_E_INVAL, AICA_E_MESH, AICA_E_RCUT, AICA_E_UNLOCATED, AICA_FP32, AICA_FP64, AicaError,
                    aica_info, aica_mesh, aica_params, check, lib)
 
-__all__ = ["DIL", "aica_build_dil", "aica_bin", "aica_forces", "aica_forces_adjoint", "aica_pairs_export",
+__all__ = ["DIL", "aica_build_dil", "aica_bin", "aica_forces", "aica_forces_noalloc", "aica_forces_adjoint", "aica_pairs_export",
            "aica_pair_counts",
            "aica_dil_export", "aica_bin_export", "AicaLJ", "AicaError", "AICA_FP32", "AICA_FP64",
            "AICA_E_INVAL", "AICA_E_MESH", "AICA_E_RCUT", "AICA_E_UNLOCATED"]
@@ -162,6 +162,28 @@ def aica_forces(dil: DIL, pos, species=None, eps=(1.0,), sigma=(1.0,), rcut=None
     check(lib().aica_forces(dil.h, C.c_void_p(pos.data_ptr()), _species_ptr(species, pos), C.byref(p),
                             C.c_void_p(F.data_ptr()), C.c_void_p(uw.data_ptr()), C.c_void_p(npairs.data_ptr()),
                             _stream(pos)))
+    return F, uw, npairs
+
+
+def aica_forces_noalloc(dil: DIL, pos, species=None, eps=(1.0,), sigma=(1.0,), rcut=None, precision="fp32",
+                        compensated=True, out=None):
+    """As aica_forces, with every device buffer of the call in the library's fixed scratch array (nothing is
+    allocated by the library).  out = (F, uw, npairs) preallocated by the caller, or None to allocate them here."""
+    import torch
+    _check_pos(pos)
+    p, keep = _params(dil.rcut if rcut is None else rcut, eps, sigma, precision, compensated)
+    dt = torch.float32 if p.precision == AICA_FP32 else torch.float64
+    if out is None:
+        out = (torch.empty((pos.shape[0], 3), dtype=dt, device=pos.device),
+               torch.empty(2, dtype=torch.float64, device=pos.device),
+               torch.empty(1, dtype=torch.int64, device=pos.device))
+    F, uw, npairs = out
+    for t, shape, want in ((F, (pos.shape[0], 3), dt), (uw, (2,), torch.float64), (npairs, (1,), torch.int64)):
+        if tuple(t.shape) != shape or t.dtype != want or t.device != pos.device or not t.is_contiguous():
+            raise ValueError(f"output tensor must be contiguous {want} of shape {shape} on {pos.device}")
+    check(lib().aica_forces_noalloc(dil.h, C.c_void_p(pos.data_ptr()), _species_ptr(species, pos), C.byref(p),
+                                    C.c_void_p(F.data_ptr()), C.c_void_p(uw.data_ptr()),
+                                    C.c_void_p(npairs.data_ptr()), _stream(pos)))
     return F, uw, npairs
 
 

@@ -25,8 +25,8 @@ ERROR_NAMES = {AICA_E_INVAL: "AICA_E_INVAL", AICA_E_MESH: "AICA_E_MESH", AICA_E_
 AICA_DIL_CLOSEST = 0
 AICA_DIL_VERTEX = 1
 
-EXPORTED = ["aica_build_dil", "aica_build_dil_ex", "aica_bin", "aica_forces", "aica_forces_adjoint",
-            "aica_dil_export", "aica_pairs_export", "aica_pair_counts", "aica_bin_export",
+EXPORTED = ["aica_build_dil", "aica_build_dil_ex", "aica_bin", "aica_forces", "aica_forces_noalloc",
+            "aica_forces_adjoint", "aica_dil_export", "aica_pairs_export", "aica_pair_counts", "aica_bin_export",
             "aica_dil_info", "aica_work_stats", "aica_profile", "aica_profile_read", "aica_last_error",
             "aica_dil_free"]
 
@@ -73,6 +73,7 @@ def lib():
         L.aica_build_dil_ex.argtypes = [C.POINTER(aica_mesh), f64, f64, i32, C.POINTER(p)]
         L.aica_bin.argtypes = [p, p, i32, i64, p]
         L.aica_forces.argtypes = [p, p, p, C.POINTER(aica_params), p, p, p, p]
+        L.aica_forces_noalloc.argtypes = [p, p, p, C.POINTER(aica_params), p, p, p, p]
         L.aica_forces_adjoint.argtypes = [p, p, p, C.POINTER(aica_params), p, f64, p, p, p, p]
         L.aica_dil_export.argtypes = [p, p, p, p, p]
         L.aica_pairs_export.argtypes = [p, p, C.POINTER(aica_params), i64, p, p, p, p, p]

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -1200,9 +1201,9 @@ static int build_tab(const aica_dil *h, const aica_params *p, LJTab &t) {
   return AICA_OK;
 }
 
-// Device buffers of one force call (the handle's grow-only workspace).  pos: [n] gathered positions;
-// own: [2n] (hi, lo) own records; jpart: [J] reaction records tagged with epoch; gpart, gnp: per-group
-// partials; red: stage-1 reduction rows.
+// Device buffers of one force call: the handle's grow-only workspace, or regions of the fixed scratch array
+// (aica_forces_noalloc).  pos: [n] gathered positions; own: [2n] (hi, lo) own records; jpart: [J] reaction
+// records tagged with epoch; gpart, gnp: per-group partials; red: stage-1 reduction rows.
 struct ForceWs {
   void *pos = nullptr, *own = nullptr, *jpart = nullptr, *gpart = nullptr, *gnp = nullptr, *red = nullptr;
   uint32_t epoch = 0;
@@ -1421,6 +1422,80 @@ int aica_forces(aica_dil *h, const void *pos_dev, const int32_t *species_dev, co
   if (params->precision == AICA_FP32)
     return forces_alloc<float>(h, pos_dev, species_dev, tab, params->compensated != 0, forces_dev, uw_dev, npairs_dev, st);
   return forces_alloc<double>(h, pos_dev, species_dev, tab, false, forces_dev, uw_dev, npairs_dev, st);
+}
+
+// ---- aica_forces without allocation: every buffer of the call lies in this fixed array (one copy per GPU,
+// held until the process ends).  Host code never passes the array's name to a kernel: it resolves the
+// array's device address once per device (hipGetSymbolAddress) and uses that.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(AICA_E_INVAL, "device index out of range for the scratch array");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(AICA_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return AICA_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+template <typename T>
+static int forces_noalloc(aica_dil *h, const void *pos_dev, const int32_t *species, const LJTab &tab, bool comp,
+                          void *forces_dev, double *uw_dev, int64_t *npairs_dev, hipStream_t st) {
+  using V4 = typename Vec4<T>::type;
+  const int64_t n = h->n, ng = h->grp.ng, J = h->jtotal;
+  const size_t b_pos = align256(sizeof(V4) * std::max<int64_t>(n, 1));
+  const size_t b_own = align256(sizeof(T) * 8 * std::max<int64_t>(n, 1));
+  const size_t b_jpart = align256(sizeof(T) * 4 * std::max<int64_t>(J, 1));
+  const size_t b_gpart = align256(sizeof(double) * 2 * std::max<int64_t>(ng, 1));
+  const size_t b_gnp = align256(16 * std::max<int64_t>(ng, 1));
+  const size_t b_red = align256(sizeof(double) * 8 * kRedBlocks);
+  const size_t need = b_pos + b_own + b_jpart + b_gpart + b_gnp + b_red;
+  if (need > kScratchBytes)
+    return fail(AICA_E_INVAL, "aica_forces_noalloc needs " + std::to_string(need) + " bytes of scratch for " +
+                                  std::to_string(n) + " molecules; the fixed scratch holds " +
+                                  std::to_string(kScratchBytes) + " (use aica_forces)");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  char *base = nullptr;
+  int rc = scratch_address(dev, (void **)&base);
+  if (rc) return rc;
+  ForceWs ws;
+  ws.pos = base;
+  ws.own = base + b_pos;
+  ws.jpart = base + b_pos + b_own;
+  ws.gpart = base + b_pos + b_own + b_jpart;
+  ws.gnp = base + b_pos + b_own + b_jpart + b_gpart;
+  ws.red = base + b_pos + b_own + b_jpart + b_gpart + b_gnp;
+  // the array keeps the last call's records: every record's tag is cleared (a fill kernel, no memset node)
+  ws.epoch = 1;
+  const int64_t words = (int64_t)(sizeof(T) * 4 * std::max<int64_t>(J, 1) / 4);
+  hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid1d(words, 256)), dim3(256), 0, st, (uint32_t *)ws.jpart, words,
+                     0xFFFFFFFFu);
+  HIPCHK(hipGetLastError());
+  if ((rc = gather_to<T>(h, pos_dev, species, tab.nsp, st, ws.pos))) return rc;
+  return forces_impl<T>(h, ws, tab, comp, forces_dev, uw_dev, npairs_dev, st, false);
+}
+
+int aica_forces_noalloc(aica_dil *h, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
+                        void *forces_dev, double *uw_dev, int64_t *npairs_dev, void *hip_stream) {
+  int rc = check_step(h, pos_dev);
+  if (rc) return rc;
+  LJTab tab;
+  if ((rc = build_tab(h, params, tab))) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (params->precision == AICA_FP32)
+    return forces_noalloc<float>(h, pos_dev, species_dev, tab, params->compensated != 0, forces_dev, uw_dev, npairs_dev, st);
+  return forces_noalloc<double>(h, pos_dev, species_dev, tab, false, forces_dev, uw_dev, npairs_dev, st);
 }
 
 int aica_pairs_export(aica_dil *h, const void *pos_dev, const aica_params *params, int64_t cap, int64_t *n_out,
