@@ -4,9 +4,12 @@ One step = one pass of the whole per-step path over one batch of synthetic input
   aica_bin (locate, CSR occupancy, work list) + aica_forces + aica_forces_adjoint,
 in FP32 pair arithmetic (compensated FP32 force sums, FP64 energy and virial).
 The same step is also timed in FP64, and the forward alone in both precisions.
+Molecules move between steps: every step bins its own position set x_k = x_0 + k delta
+(delta a seeded displacement of about 0.005 sigma per coordinate, the distance an LJ fluid
+at T* = 1 covers in one step of dt = 0.005), all sets resident in HBM before timing.
 
-Prints ONE JSON line (rank 0).  `value` = npairs * steps / (timed seconds) for the
-FP32 forward+adjoint step.  `roofline` is the dominant kernel's algorithmic
+Prints ONE JSON line (rank 0).  `value` = (sum of npairs over the timed steps) / (timed
+seconds) for the FP32 forward+adjoint step.  `roofline` is the dominant kernel's algorithmic
 FLOP rate (HIP events on the stream the kernel runs on) against the FP32 vector
 peak; `cpu_baseline` is the FP64 oracle timed on a bounded sample of rows.
 """
@@ -54,7 +57,7 @@ def workload(name):
 
 
 # Kernel sources whose digest ties the traffic counters to the code they were measured on.
-KERNEL_SOURCES = ["aica_pair.inc", "aica_device.hip", "aica_kernels.h", "aica_adjoint.inc"]
+KERNEL_SOURCES = ["aica_pair.inc", "aica_adjoint_pair.inc", "aica_device.hip", "aica_kernels.h", "aica_adjoint.inc"]
 
 
 def kernel_digest():
@@ -87,7 +90,37 @@ def measured_traffic(kernel, workload):
     return rows.get(kernel)
 
 
-PAIR_KERNELS = {"pair_fwd": "k_pair<float, 0, 0, true, false>", "pair_adj": "k_pair<float, 0, 2, true, false>"}
+PAIR_KERNELS = {"pair_fwd": "k_pair<float, 0, 0, true, false>", "pair_adj": "k_pair_adj<float, 0, false>"}
+TIMERS = ("pair_fwd", "pair_adj", "bin", "finalize", "finalize_adj")
+
+
+def moving_sets(wl, count, step=0.005, seed=11):
+    """Positions of `count` consecutive steps, x_k = x_0 + k delta with delta ~ N(0, step) per coordinate
+    (seeded), rounded to the position grid, wrapped on periodic axes and reflected at walls.  With rotating
+    referral only the axis periodic by translation (z) moves."""
+    from paper_cs_0702131_amd import workloads as W
+    delta = np.random.default_rng(seed).normal(0.0, step, size=wl.x.shape)
+    lo, hi = np.asarray(wl.mesh.lo, float), np.asarray(wl.mesh.hi, float)
+    periodic = set(wl.periodic_axes)
+    if wl.rotations is not None:
+        delta[:, :2] = 0.0
+        periodic = {2}
+    sets = [wl.x]
+    for k in range(1, count):
+        x = wl.x + k * delta
+        for a in range(3):
+            if a in periodic:
+                x[:, a] = lo[a] + np.mod(x[:, a] - lo[a], hi[a] - lo[a])
+            else:
+                x[:, a] = np.where(x[:, a] < lo[a], 2 * lo[a] - x[:, a], x[:, a])
+                x[:, a] = np.where(x[:, a] > hi[a], 2 * hi[a] - x[:, a], x[:, a])
+        x = W.qround(x)
+        for a in range(3):
+            if a in periodic:
+                x[:, a] = np.where(x[:, a] >= hi[a], x[:, a] - (hi[a] - lo[a]), x[:, a])
+            x[:, a] = np.clip(x[:, a], lo[a], hi[a])
+        sets.append(x)
+    return sets
 
 
 def measured_valu_issue(kernel, workload):
@@ -107,31 +140,68 @@ def measured_valu_issue(kernel, workload):
     return frac if digest == kernel_digest() else None
 
 
-def timed_steps(A, d, x, sp, wl, G, precision, steps, warmup, adjoint=True):
+def timed_steps(A, d, xs, sp, wl, G, precision, steps, warmup, adjoint=True):
+    """Warm-up steps on xs[0 .. warmup-1], then `steps` timed steps on xs[warmup ..], each binning its own
+    position set.  Returns the time, the per-kernel timers, npairs of every timed step and the routes by which
+    each timed binning located its molecules."""
     import torch
-    st = torch.cuda.current_stream()
-    for _ in range(warmup):
+    for k in range(warmup):
+        x = xs[k]
         A.aica_bin(d, x)
-        F, uw, npairs = A.aica_forces(d, x, sp, wl.eps, wl.sigma, precision=precision)
+        A.aica_forces(d, x, sp, wl.eps, wl.sigma, precision=precision)
         if adjoint:
             A.aica_forces_adjoint(d, x, G, GAMMA, sp, wl.eps, wl.sigma, precision=precision)
     torch.cuda.synchronize()
-    for k in ("pair_fwd", "pair_adj", "bin", "finalize"):
+    for k in TIMERS:
         d.profile_read(k, reset=True)
     d.profile(True)
     torch.cuda.synchronize()
+    counts, routes = [], []
     t0 = time.perf_counter()
-    gx = None
-    for _ in range(steps):
-        A.aica_bin(d, x)
+    for k in range(steps):
+        x = xs[warmup + k]
+        A.aica_bin(d, x)  # synchronises once (unlocated and reaction-slot counts): the route counts are host-side
+        inf = d.info()
+        routes.append((inf["located_ball"], inf["located_record"], inf["located_search"]))
         F, uw, npairs = A.aica_forces(d, x, sp, wl.eps, wl.sigma, precision=precision)
+        counts.append(npairs)
         if adjoint:
-            gx = A.aica_forces_adjoint(d, x, G, GAMMA, sp, wl.eps, wl.sigma, precision=precision)[0]
+            A.aica_forces_adjoint(d, x, G, GAMMA, sp, wl.eps, wl.sigma, precision=precision)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     d.profile(False)
-    prof = {k: d.profile_read(k, reset=True) for k in ("pair_fwd", "pair_adj", "bin", "finalize")}
-    return t, prof, F, uw, int(npairs.item()), gx
+    prof = {k: d.profile_read(k, reset=True) for k in TIMERS}
+    return t, prof, [int(c.item()) for c in counts], routes
+
+
+def evaluate(A, d, x, sp, wl, G, precision):
+    """Forces, U/W, npairs and dL/dx on one position set (untimed; for the error statements)."""
+    A.aica_bin(d, x)
+    F, uw, npairs = A.aica_forces(d, x, sp, wl.eps, wl.sigma, precision=precision)
+    gx, ge, gs = A.aica_forces_adjoint(d, x, G, GAMMA, sp, wl.eps, wl.sigma, precision=precision)
+    return (F.double().cpu().numpy(), uw.cpu().numpy(), int(npairs.item()), gx.double().cpu().numpy(),
+            ge.cpu().numpy(), gs.cpu().numpy())
+
+
+def stored_binary_errors(wl, G, results):
+    """Errors of the GPU adjoint against the stored FP64 oracle results of the binary mixture (dL/dx on
+    1,024 fixed rows relative to the rms over all molecules; the four parameter gradients against the
+    oracle's analytic values and against its central differences at h = 1e-6; L)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_binary_adjoint as M
+    g = M.read()
+    assert wl.n == int(g["n"]) and GAMMA == wl.extra["gamma"]
+    out = {}
+    for prec, (F, uw, gx, ge, gs) in results.items():
+        L = float((G * F).sum() + GAMMA * uw[0])
+        out[f"stored_{prec}_dLdx_rows"] = float(np.abs(gx[g["rows"]] - g["dLdx"]).max() / g["rms_dLdx_all"])
+        out[f"stored_{prec}_dparams"] = float(max((np.abs(ge - g["grad_eps"]) / np.abs(g["grad_eps"])).max(),
+                                                  (np.abs(gs - g["grad_sigma"]) / np.abs(g["grad_sigma"])).max()))
+        out[f"stored_{prec}_dparams_vs_fd"] = float(max((np.abs(ge - g["fd_eps"]) / np.abs(g["fd_eps"])).max(),
+                                                        (np.abs(gs - g["fd_sigma"]) / np.abs(g["fd_sigma"])).max()))
+        out[f"stored_{prec}_L"] = abs(L - g["L"]) / abs(g["L"])
+    out["stored_rows"] = len(g["rows"])
+    return out
 
 
 def cpu_baseline(wl, seconds_target, F32, F64, G, gx32, gx64, rng_seed=7):
@@ -197,7 +267,7 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs (processor referral "
+        print(json.dumps({"error": "bench.py measures one GPU only; multi-GPU runs (processor referral "
                                    "and halo exchange) are not part of it", "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -214,48 +284,54 @@ def main():
     log(f"interaction lists: {info['n_dil']} cell pairs in {info['build_seconds']:.1f}s")
 
     dev = torch.device("cuda:0")
-    x32 = torch.tensor(wl.x, dtype=torch.float32, device=dev)
-    x64 = torch.tensor(wl.x, dtype=torch.float64, device=dev)
+    S = args.warmup + args.steps
+    t0 = time.perf_counter()
+    sets = moving_sets(wl, S)
+    xs32 = [torch.tensor(x, dtype=torch.float32, device=dev) for x in sets]
+    xs64 = None if args.no_fp64 else [torch.tensor(x, dtype=torch.float64, device=dev) for x in sets]
+    del sets
+    log(f"{S} moving position sets resident in HBM ({time.perf_counter() - t0:.1f}s)")
     sp = torch.tensor(wl.species, dtype=torch.int32, device=dev)
     G = wl.extra.get("G")
     if G is None:
         G = W.qround(np.random.default_rng(9).standard_normal((wl.n, 3)))
     G32 = torch.tensor(G, dtype=torch.float32, device=dev)
     G64 = torch.tensor(G, dtype=torch.float64, device=dev)
-    A.aica_bin(d, x32)
-    A.aica_forces(d, x32, sp, wl.eps, wl.sigma, precision="fp32")
+
+    res = {}
+    t, prof, counts, routes = timed_steps(A, d, xs32, sp, wl, G32, "fp32", args.steps, args.warmup)
+    res["fp32_fwd_adj"] = (t, prof, counts)
+    log(f"fp32 fwd+adj: {1e3 * t / args.steps:.3f} ms/step, npairs {counts}")
+    t, prof, c, _ = timed_steps(A, d, xs32, sp, wl, G32, "fp32", args.steps, args.warmup, adjoint=False)
+    res["fp32_fwd"] = (t, prof, c)
+    assert c == counts
+    if xs64 is not None:
+        t, prof, c, _ = timed_steps(A, d, xs64, sp, wl, G64, "fp64", args.steps, args.warmup)
+        res["fp64_fwd_adj"] = (t, prof, c)
+        assert c == counts, (c, counts)
+        t, prof, c, _ = timed_steps(A, d, xs64, sp, wl, G64, "fp64", args.steps, args.warmup, adjoint=False)
+        res["fp64_fwd"] = (t, prof, c)
+        log(f"fp64 fwd+adj: {1e3 * res['fp64_fwd_adj'][0] / args.steps:.3f} ms/step")
+
+    # error statements and work counts on the first position set (untimed)
+    F32n, uw32, npairs, gx32n, ge32, gs32 = evaluate(A, d, xs32[0], sp, wl, G32, "fp32")
     info = d.info()
     dil_cand, lane_pairs = d.work_stats()
     log(f"groups {info['n_groups']} group pairs {info['n_group_pairs']} ({info['group_seconds']:.1f}s); "
         f"DIL candidates {dil_cand}, executed lane pairs {lane_pairs}")
-
-    res = {}
-    t, prof, F32, uw32, npairs, gx32 = timed_steps(A, d, x32, sp, wl, G32, "fp32", args.steps, args.warmup)
-    res["fp32_fwd_adj"] = (t, prof)
-    log(f"fp32 fwd+adj: {1e3 * t / args.steps:.3f} ms/step, npairs {npairs}")
-    gx32n = gx32.double().cpu().numpy()
-    t, prof, F32, uw32, _, _ = timed_steps(A, d, x32, sp, wl, G32, "fp32", args.steps, 1, adjoint=False)
-    res["fp32_fwd"] = (t, prof)
-    F32n = F32.double().cpu().numpy()
     F64n = gx64n = None
-    if not args.no_fp64:
-        t, prof, F64, uw64, npairs64, gx64 = timed_steps(A, d, x64, sp, wl, G64, "fp64", args.steps, args.warmup)
-        res["fp64_fwd_adj"] = (t, prof)
-        gx64n = gx64.cpu().numpy()
-        t, prof, F64, uw64, npairs64, _ = timed_steps(A, d, x64, sp, wl, G64, "fp64", args.steps, 1,
-                                                      adjoint=False)
-        res["fp64_fwd"] = (t, prof)
-        F64n = F64.cpu().numpy()
+    if xs64 is not None:
+        F64n, uw64, npairs64, gx64n, ge64, gs64 = evaluate(A, d, xs64[0], sp, wl, G64, "fp64")
         assert npairs64 == npairs, (npairs64, npairs)
 
     K = args.steps
-    t_main, prof_main = res["fp32_fwd_adj"]
-    value = npairs * K / t_main
+    t_main, prof_main, counts_main = res["fp32_fwd_adj"]
+    value = sum(counts_main) / t_main
     breakdown = {}
-    for key, (t, prof) in res.items():
-        breakdown[key] = {"ms_per_step": 1e3 * t / K, "pairs_per_s": npairs * K / t,
+    for key, (t, prof, c) in res.items():
+        breakdown[key] = {"ms_per_step": 1e3 * t / K, "pairs_per_s": sum(c) / t,
                           **{f"{k}_ms": v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}}
-    # dominant kernel of the FP32 step and its algorithmic FLOP rate
+    # dominant kernel of the FP32 step and its algorithmic FLOP rate (work counts of the first set)
     fwd_ms = prof_main["pair_fwd"][0] / prof_main["pair_fwd"][1]
     adj_ms = prof_main["pair_adj"][0] / prof_main["pair_adj"][1]
     rejected = dil_cand - npairs
@@ -287,12 +363,19 @@ def main():
         errors["dW_fp32_vs_fp64"] = float(abs(uw32[1].item() - uw64[1].item()) / abs(uw64[1].item()))
         # every row of dL/dx (the FP64 path matches the oracle to ~1e-15 on the sampled rows)
         errors["e_dLdx_fp32_vs_fp64_gpu"] = float(np.abs(gx32n - gx64n).max() / np.sqrt((gx64n ** 2).mean()))
+    if args.workload == "binary":
+        res_b = {"fp32": (F32n, uw32, gx32n, ge32, gs32)}
+        if F64n is not None:
+            res_b["fp64"] = (F64n, uw64, gx64n, ge64, gs64)
+        errors.update(stored_binary_errors(wl, G, res_b))
 
     out = {"metric": METRIC, "value": value, "unit": "pair interactions/s", "n_gpus": 1, "steps": K,
            "warmup": args.warmup, "ms_per_step": 1e3 * t_main / K, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
            "config": {"workload": wl.name, "cells": wl.mesh.n_cells, "molecules": wl.n, "npairs": npairs,
-                      "step": "aica_bin + aica_forces + aica_forces_adjoint", "parallelism": "single GPU",
+                      "npairs_per_step": counts_main, "located_ball_record_search": routes,
+                      "step": "aica_bin + aica_forces + aica_forces_adjoint on moving molecules",
+                      "parallelism": "single GPU",
                       "dil_cell_pairs": info["n_dil"], "dil_candidates": dil_cand, "lane_pairs": lane_pairs,
                       "lane_efficiency": npairs / max(lane_pairs, 1)},
            "breakdown": breakdown, "errors": errors, "roofline": roofline, "cpu_baseline": cpu}

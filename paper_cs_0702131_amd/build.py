@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libaica.so")
 SOURCES = ["aica_device.hip", "aica_setup.cpp"]
-DEPS = SOURCES + ["aica_internal.h", "aica_kernels.h", "aica_adjoint.inc", "aica_pair.inc"]
+DEPS = SOURCES + ["aica_internal.h", "aica_kernels.h", "aica_adjoint.inc", "aica_adjoint_pair.inc", "aica_pair.inc"]
 
 # Packed FP32 instructions are disabled (the compiler would otherwise form v_pk_* from scalar code).
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",

@@ -35,3 +35,27 @@ def test_counter_summaries_follow_the_source_digest(monkeypatch):
     assert bench.measured_traffic("pair_adj", "channel") is None
     assert bench.measured_valu_issue("pair_adj", "channel") is None
     assert bench.measured_traffic("pair_adj", "no_such_workload") is None
+
+
+def test_moving_sets_stay_in_the_mesh_on_the_grid():
+    """The benchmark's per-step position sets: set 0 is the workload, later sets move by k delta (about
+    0.005 sigma per step and coordinate), stay on the 2^-15 position grid, inside the box, wrapped on the
+    periodic axes and reflected at the walls."""
+    import numpy as np
+
+    from paper_cs_0702131_amd import workloads as W
+    for wl in (W.config1(), W.small_random(N=300, periodic_axes=(0, 2), seed=3)):
+        sets = bench.moving_sets(wl, 6)
+        assert len(sets) == 6 and sets[0] is wl.x
+        lo, hi = wl.mesh.lo, wl.mesh.hi
+        for k, x in enumerate(sets[1:], start=1):
+            assert np.all(x >= lo) and np.all(x <= hi)
+            assert np.array_equal(W.qround(x), x)
+            d = x - wl.x
+            for a in wl.periodic_axes:
+                L = hi[a] - lo[a]
+                d[:, a] -= L * np.round(d[:, a] / L)
+            step = np.sqrt((d ** 2).mean())
+            assert 0.5 * 0.005 * k < step < 1.5 * 0.005 * k, (k, step)
+        for a in wl.periodic_axes:
+            assert all(np.all(x[:, a] < hi[a]) for x in sets)

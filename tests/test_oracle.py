@@ -670,3 +670,22 @@ def test_invalid_referring_transforms(oracle):
     # rotation about z with a translation along x: the two do not commute
     with pytest.raises(ValueError):
         oracle.forces(x, [0, 0], [1.0], [1.0], 2.5, np.array([[0.0, 0, 0], [30.0, 0, 0]]), rot=ok)
+
+
+def test_binary_full_size_stored_results():
+    """The stored FP64 oracle results of the 219,488-molecule binary mixture (written by
+    tests/golden/make_binary_adjoint.py, about 2.3 h of CPU): the analytic parameter gradients agree with
+    the central differences of the oracle's loss (h = 1e-6) to 1e-7, they satisfy the eps-homogeneity sum
+    rule against the stored L, and the stored rows are the ones the fixed seed draws."""
+    import sys
+    sys.path.insert(0, GOLD)
+    import make_binary_adjoint as M
+    g = M.read()
+    assert int(g["n"]) == 219488 and len(g["rows"]) == M.NROWS
+    assert np.array_equal(g["rows"], M.sample_rows(int(g["n"])))
+    for a, f in ((g["grad_eps"], g["fd_eps"]), (g["grad_sigma"], g["fd_sigma"])):
+        assert np.all(np.abs(a - f) <= 1e-7 * np.abs(f)), (a, f)
+    assert np.isfinite(g["dLdx"]).all() and g["rms_dLdx_all"] > 0
+    # L is linear in every eps_ab and eps_ab is homogeneous of degree one in the species' eps: with
+    # eps = (1, 0.5), sum_s eps_s dL/deps_s = L
+    assert abs(1.0 * g["grad_eps"][0] + 0.5 * g["grad_eps"][1] - g["L"]) < 1e-10 * abs(g["L"])
