@@ -200,7 +200,9 @@ __device__ bool point_in_rec(const double *p, const double *R, double tau) {
 
 // FP32 copies of the cell records for the previous-cell test, fixed stride kR32 float4 per sorted cell:
 //   [0] (nf, a.x, a.y, a.z) with a the FP32-rounded vertex mean; [1] (cc - a, 0);
-//   [2 .. 2 + nf) (fc_k - a, len_k); then the face loops, one vertex (v - a, 0) per float4.
+//   [2 .. 2 + nf) (fc_k - a, len_k); then the face loops, one vertex (v - a, 0) per float4, except that the
+//   first vertex of face k's loop carries in .w the sorted id of the cell across face k (int bits; -1 on
+//   a boundary face).
 // A point is accepted when some tetrahedron contains it with every orientation above 1e-4 of that
 // tetrahedron's own (FP32) orientation.  The FP32 rounding of the records and of the orientations is
 // below 1e-5 of that scale, so an accepted point is strictly inside in exact arithmetic too (the FP64
@@ -214,7 +216,9 @@ __device__ __forceinline__ float orient3f(const float *a, const float *b, const 
   return u0 * (v1 * w2 - v2 * w1) + u1 * (v2 * w0 - v0 * w2) + u2 * (v0 * w1 - v1 * w0);
 }
 
-__device__ bool surely_in_rec32(const double *p, const float4 *R) {
+// across (optional): the sorted id of the cell across the face whose centroid direction best matches
+// p - cc (the face a molecule that left the cell has most likely crossed), -1 on a boundary face.
+__device__ bool surely_in_rec32(const double *p, const float4 *R, int *across = nullptr) {
   const float4 h = R[0], h2 = R[1];
   const int nf = (int)h.x;
   const float pr[3] = {(float)(p[0] - (double)h.y), (float)(p[1] - (double)h.z), (float)(p[2] - (double)h.w)};
@@ -233,6 +237,7 @@ __device__ bool surely_in_rec32(const double *p, const float4 *R) {
     }
     off += (int)f.w;
   }
+  if (across) *across = __float_as_int(R[2 + nf + boff].w);
   auto fan = [&](int k, int voff) -> bool {
     const float4 f = R[2 + k];
     const float fc[3] = {f.x, f.y, f.z};
@@ -303,9 +308,11 @@ __device__ float4 inner_ball(const double *p, const float4 *R) {
 // Locate each molecule: cell_of[i] = sorted index of the cell that contains x_i, in two kernels so that
 // the rare slow cases do not hold up whole waves.
 // k_locate_fast visits molecules in the order trav (the previous binning's sorted order, so that
-// neighbouring threads read neighbouring cell records): a molecule that the FP32 records show strictly
-// inside its previous cell (hint) is in no other cell; every other molecule goes to a list.
-// k_locate_slow takes that list: the FP64 previous-cell test; then the cells across the previous cell's
+// neighbouring threads read neighbouring cell records), kLocPerLane per lane: a molecule still inside the
+// ball kept from its last record test is in its previous cell (hint); the others are compacted in LDS and
+// tested 64 at a time against the FP32 records (the previous cell, then the cell across the face most
+// likely crossed: a molecule that a record shows strictly inside a cell is in no other); every other
+// molecule goes to a list.  k_locate_slow takes that list: the FP64 previous-cell test; then the cells across the previous cell's
 // faces (a molecule that left its cell has crossed one of them: the paper's membership tracking), each
 // accepted only when the point is strictly inside; then every cell whose padded box holds the point, in
 // ascending mesh cell id (the lowest containing cell wins a tie on a shared face, edge or vertex).  Without FP32 records (a cell too large for the fixed stride) or without a previous binning
@@ -315,44 +322,93 @@ __device__ float4 inner_ball(const double *p, const float4 *R) {
 // caller index and there is no hint), so that only the positions are read out of order.
 constexpr int kRouteSlots = 64;
 
+constexpr int kLocPerLane = 4;  // molecules per lane in the fast kernel
+
 template <typename PT>
-__global__ void k_locate_fast(const PT *__restrict__ pos, int64_t n, const int32_t *__restrict__ trav,
-                              const int32_t *__restrict__ hint, const float4 *__restrict__ rec32,
-                              float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ rank_t,
-                              int32_t *__restrict__ count, unsigned long long *__restrict__ nslow,
-                              int32_t *__restrict__ slow, unsigned long long *__restrict__ routes) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int how = -1;  // 0: inside its ball, 1: the record test, 2: to the slow kernel
-  if (t < n) {
-    const int64_t i = trav ? trav[t] : t;
-    const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
-    const int32_t h0 = hint ? hint[t] : -1;
-    how = 2;
-    if (h0 >= 0 && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
-      // still inside the ball found inside this cell when it was last tested: no record needed
-      const float4 b = ref[i];
-      const double e0 = p[0] - (double)b.x, e1 = p[1] - (double)b.y, e2 = p[2] - (double)b.z;
-      if (b.w > 0.f && e0 * e0 + e1 * e1 + e2 * e2 < (double)b.w * (double)b.w) {
-        how = 0;
-      } else if (rec32) {
-        const float4 *R = rec32 + (int64_t)kR32 * h0;
-        if (surely_in_rec32(p, R)) {
+__global__ __launch_bounds__(256) void k_locate_fast(
+    const PT *__restrict__ pos, int64_t n, const int32_t *__restrict__ trav, const int32_t *__restrict__ hint,
+    const float4 *__restrict__ rec32, float4 *__restrict__ ref, int32_t *__restrict__ cell_t,
+    int32_t *__restrict__ rank_t, int32_t *__restrict__ count, unsigned long long *__restrict__ nslow,
+    int32_t *__restrict__ slow, unsigned long long *__restrict__ routes) {
+  constexpr int kSpan = 64 * kLocPerLane;  // molecules per wave
+  __shared__ int32_t rec_l[4][kSpan];      // per wave: slots (relative to the wave's first) for the records
+  __shared__ int32_t slow_l[4][kSpan];     // per wave: slots for the slow kernel
+  const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+  const int64_t base = ((int64_t)blockIdx.x * 4 + w) * kSpan;
+  int nr = 0, ns = 0;  // wave-uniform list lengths
+  auto push = [&](int32_t *L, int &len, bool take, int val) {
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(take);
+    if (take) L[len + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = val;
+    len += (int)__builtin_popcountll(m);
+  };
+  // ---- the ball test, kLocPerLane molecules per lane
+  for (int k = 0; k < kLocPerLane; ++k) {
+    const int off = k * 64 + lane;
+    const int64_t t = base + off;
+    int how = -1;  // 0: inside its ball, 1: to the record test, 2: to the slow kernel
+    if (t < n) {
+      const int64_t i = trav ? trav[t] : t;
+      const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
+      const int32_t h0 = hint ? hint[t] : -1;
+      how = 2;
+      if (h0 >= 0 && isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2])) {
+        // still inside the ball found inside this cell when it was last tested: no record needed
+        const float4 b = ref[i];
+        const double e0 = p[0] - (double)b.x, e1 = p[1] - (double)b.y, e2 = p[2] - (double)b.z;
+        if (b.w > 0.f && e0 * e0 + e1 * e1 + e2 * e2 < (double)b.w * (double)b.w) {
+          how = 0;
+          cell_t[t] = h0;
+          rank_t[t] = atomicAdd(&count[h0], 1);
+        } else if (rec32) {
           how = 1;
-          ref[i] = inner_ball(p, R);
         }
       }
     }
-    if (how < 2) {
-      cell_t[t] = h0;
-      rank_t[t] = atomicAdd(&count[h0], 1);
-    } else {
-      slow[atomicAdd(nslow, 1ull)] = (int32_t)t;
-    }
+    push(rec_l[w], nr, how == 1, off);
+    push(slow_l[w], ns, how == 2, off);
   }
-  // how many needed the record test (the rest: inside their ball or sent to the slow kernel), one atomic
-  // per wave that had any, spread over kRouteSlots counters so that the waves do not queue on one address
-  const unsigned long long m1 = __builtin_amdgcn_ballot_w64(how == 1);
-  if ((threadIdx.x & 63) == 0 && m1) atomicAdd(routes + blockIdx.x % kRouteSlots, (unsigned long long)__builtin_popcountll(m1));
+  wave_lds_sync();
+  // ---- the FP32 records of the molecules that left their ball, 64 at a time on a compacted list: the
+  // previous cell, then the cell across the face most likely crossed
+  int nrec = 0;
+  for (int b = 0; b < nr; b += 64) {
+    int how = -1;
+    int off = 0;
+    if (b + lane < nr) {
+      off = rec_l[w][b + lane];
+      const int64_t t = base + off;
+      const int64_t i = trav[t];
+      const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
+      const int32_t h0 = hint[t];
+      int32_t found = -1, across = -1;
+      if (surely_in_rec32(p, rec32 + (int64_t)kR32 * h0, &across)) {
+        found = h0;
+      } else if (across >= 0 && surely_in_rec32(p, rec32 + (int64_t)kR32 * across)) {
+        found = across;
+      }
+      if (found >= 0) {
+        how = 1;
+        ref[i] = inner_ball(p, rec32 + (int64_t)kR32 * found);
+        cell_t[t] = found;
+        rank_t[t] = atomicAdd(&count[found], 1);
+      } else {
+        how = 2;
+      }
+    }
+    nrec += (int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(how == 1));
+    push(slow_l[w], ns, how == 2, off);
+  }
+  wave_lds_sync();
+  // ---- the wave's share of the slow list (one atomic), and of the route counters (spread over
+  // kRouteSlots addresses so that the waves do not queue on one)
+  if (ns > 0) {
+    unsigned long long start = 0;
+    if (lane == 0) start = atomicAdd(nslow, (unsigned long long)ns);
+    start = __shfl(start, 0, 64);
+    for (int b = lane; b < ns; b += 64) slow[start + b] = (int32_t)(base + slow_l[w][b]);
+  }
+  if (lane == 0 && nrec > 0)
+    atomicAdd(routes + (blockIdx.x * 4 + w) % kRouteSlots, (unsigned long long)nrec);
 }
 
 template <typename PT>
@@ -866,6 +922,16 @@ static int upload_geometry(aica_dil *h) {
           }
           for (int64_t j = 0; j < nv; ++j)
             O[2 + nf + j] = make_float4((float)(V[3 * j] - a[0]), (float)(V[3 * j + 1] - a[1]), (float)(V[3 * j + 2] - a[2]), 0.f);
+          // the cell across each face, on the first vertex of the face's loop
+          const int64_t c = h->order[s];
+          int64_t v0 = 0;
+          for (int64_t k = 0; k < nf; ++k) {
+            const int32_t f = g.cf[g.cf_off[c] + k];
+            const int64_t other = g.own[f] == c ? g.nei[f] : g.own[f];
+            const int32_t across = g.nei[f] >= 0 && other >= 0 ? (int32_t)h->rank[other] : -1;
+            O[2 + nf + v0].w = __builtin_bit_cast(float, across);
+            v0 += (int64_t)LEN[k];
+          }
         }
       });
       if ((rc = upload(h->d_rec32, r32))) return rc;
@@ -1098,7 +1164,8 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
 
   ProfScope ps(h, "bin", st);
   unsigned long long *status = h->d_status.as<unsigned long long>();
-  // status: [0] unlocated, [1] over-full cells, [2] slow-kernel molecules, [8 ..) record-test counters
+  // status: [0] unlocated, [1] over-full cells, [2] slow-kernel molecules, [8 ..) counters of the molecules
+  // the records located
   hipLaunchKernelGGL((k_fill<unsigned long long>), dim3(1), dim3(8 + kRouteSlots), 0, st, status,
                      (int64_t)(8 + kRouteSlots), 0ull);
   unsigned long long *routes = status + 8;
@@ -1116,9 +1183,9 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
     int32_t *slow = h->d_slow.as<int32_t>();
     unsigned long long *nslow = status + 2;
 #define AICA_LOCATE(PT)                                                                                            \
-  hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256)), dim3(256), 0, st, (const PT *)pos_dev, n, trav, hint, \
-                     r32, h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_rank.as<int32_t>(),             \
-                     h->d_count.as<int32_t>(), nslow, slow, routes);                                                \
+  hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256 * kLocPerLane)), dim3(256), 0, st, (const PT *)pos_dev, \
+                     n, trav, hint, r32, h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_rank.as<int32_t>(), \
+                     h->d_count.as<int32_t>(), nslow, slow, routes);                                               \
   hipLaunchKernelGGL((k_locate_slow<PT>), dim3(std::min<int64_t>(grid1d(n, 128), 2048)), dim3(128), 0, st, (const PT *)pos_dev, nslow, slow, \
                      trav, hint, h->d_rec_off.as<int64_t>(), h->d_rec.as<double>(), h->d_nbr_off.as<int64_t>(),   \
                      h->d_nbr.as<int32_t>(), h->d_bb.as<double>(), h->d_gb_off.as<int64_t>(),                       \

@@ -368,14 +368,15 @@ def test_binning_ties_on_faces_edges_vertices(A, oracle):
 def test_binning_balls_and_routes(A, oracle):
     """Tracking (the paper's membership kept from step to step): the first binning searches, the second
     tests every molecule against its previous cell's record and keeps a ball inside that cell, the third
-    (same positions) needs no geometry at all; small moves then mix the routes.  Every binning equals
-    brute-force location, and the routes add up to n."""
+    (same positions) needs no geometry at all; small moves then mix the routes, and a molecule that crossed
+    a face is mostly located by the record of the cell across it.  Every binning equals brute-force
+    location, and the routes add up to n."""
     import torch
     wl = W.small_random(n_mesh=(5, 4, 5), L=(10.0, 8.0, 10.0), N=500, seed=31, mesh_jitter=0.25)
     d = A.DIL(wl.mesh, wl.rcut)
     x = wl.x.copy()
     rng = np.random.default_rng(32)
-    routes = []
+    routes, cells = [], []
     for step in range(6):
         if step >= 3:  # moves of up to 0.15 per axis, wrapped into the periodic box
             x = W.qround(W.wrap(x + rng.uniform(-0.15, 0.15, size=x.shape), wl.box_lo, wl.box_hi,
@@ -385,6 +386,7 @@ def test_binning_balls_and_routes(A, oracle):
         A.aica_bin(d, t)
         cell_of, _, _ = A.aica_bin_export(d, len(x))
         assert np.array_equal(cell_of, oracle.locate(wl.mesh, x)), step
+        cells.append(cell_of)
         inf = d.info()
         r = (inf["located_ball"], inf["located_record"], inf["located_search"])
         routes.append(r)
@@ -394,6 +396,11 @@ def test_binning_balls_and_routes(A, oracle):
     assert routes[1][0] == 0 and routes[1][1] >= 0.95 * len(x)
     assert routes[2][0] >= 0.95 * len(x)
     assert routes[5][0] > 0 and routes[5][1] + routes[5][2] > 0
+    # a molecule that crossed a face is mostly found by the FP32 record of the cell across the face it
+    # most likely crossed, without the slow path
+    moved = int((cells[5] != cells[4]).sum())
+    _note(f"molecules that changed cells in the last move: {moved}; slow path: {routes[5][2]}")
+    assert moved > 20 and routes[5][2] < 0.5 * moved
 
 
 def test_cells_at_the_occupancy_limit(A, oracle):
