@@ -312,11 +312,12 @@ __device__ float4 inner_ball(const double *p, const float4 *R) {
 // ball kept from its last record test is in its previous cell (hint); the others are compacted in LDS and
 // tested 64 at a time against the FP32 records (the previous cell, then the cell across the face most
 // likely crossed: a molecule that a record shows strictly inside a cell is in no other); every other
-// molecule goes to a list.  k_locate_slow takes that list: the FP64 previous-cell test; then the cells across the previous cell's
-// faces (a molecule that left its cell has crossed one of them: the paper's membership tracking), each
-// accepted only when the point is strictly inside; then every cell whose padded box holds the point, in
-// ascending mesh cell id (the lowest containing cell wins a tie on a shared face, edge or vertex).  Without FP32 records (a cell too large for the fixed stride) or without a previous binning
-// every molecule takes the slow path.
+// molecule goes to a list.  k_locate_slow takes that list, one wave per molecule: the FP64 previous-cell
+// test and the cells across the previous cell's faces (a molecule that left its cell has crossed one of
+// them: the paper's membership tracking), each accepted only when the point is strictly inside; then
+// every cell whose padded box holds the point, in ascending mesh cell id (the lowest containing cell wins
+// a tie on a shared face, edge or vertex).  Without FP32 records (a cell too large for the fixed stride)
+// or without a previous binning every molecule takes the slow path.
 // Both kernels index their state by t, the molecule's slot in the previous binning's sorted order
 // (trav[t] = its caller index, hint[t] = its previous cell; without a previous binning t is the
 // caller index and there is no hint), so that only the positions are read out of order.
@@ -411,69 +412,96 @@ __global__ __launch_bounds__(256) void k_locate_fast(
     atomicAdd(routes + (blockIdx.x * 4 + w) % kRouteSlots, (unsigned long long)nrec);
 }
 
-template <typename PT>
-__device__ void locate_slow_one(const PT *__restrict__ pos, const int64_t t, const int32_t *__restrict__ trav,
-                                const int32_t *__restrict__ hint, const int64_t *__restrict__ rec_off,
-                                const double *__restrict__ rec, const int64_t *__restrict__ nbr_off,
-                                const int32_t *__restrict__ nbr, const double *__restrict__ bb,
-                                const int64_t *__restrict__ gb_off, const int32_t *__restrict__ gb_cell, double glo0,
-                                double glo1, double glo2, double gh, int64_t nb0, int64_t nb1, int64_t nb2,
-                                float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ rank_t,
-                                int32_t *__restrict__ count, unsigned long long *__restrict__ status) {
-  const int64_t i = trav ? trav[t] : t;
-  const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
-  const bool finite = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
+// The slow path for one molecule at p with previous cell h0 (-1: none): the previous cell and the cells
+// across its faces, each accepted only when p is strictly inside (so at most one accepts), then the cells of
+// the background bin whose padded box holds p, in ascending mesh cell id, the first containing one.  WAVE:
+// the wave's lanes test up to 64 candidates side by side (the lowest accepting lane is the first accepting
+// candidate, so the answer is that of testing them one after another); with FP32 records the cells across
+// the faces are first tried with the FP32 test, which only accepts points strictly inside.  Otherwise one
+// lane tests the candidates in turn.
+template <bool WAVE>
+__device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restrict__ rec32,
+                             const int64_t *__restrict__ rec_off, const double *__restrict__ rec,
+                             const int64_t *__restrict__ nbr_off, const int32_t *__restrict__ nbr,
+                             const double *__restrict__ bb, const int64_t *__restrict__ gb_off,
+                             const int32_t *__restrict__ gb_cell, double glo0, double glo1, double glo2, double gh,
+                             int64_t nb0, int64_t nb1, int64_t nb2) {
+  constexpr int kStep = WAVE ? 64 : 1;
+  const int lane = WAVE ? (int)(threadIdx.x & 63) : 0;
   int32_t found = -1;
-  const int32_t h0 = hint ? hint[t] : -1;
-  if (h0 >= 0 && finite) {
-    if (point_in_rec(p, rec + rec_off[h0], -1e-9)) {
-      found = h0;
-    } else {
-      for (int64_t k = nbr_off[h0]; k < nbr_off[h0 + 1]; ++k)
-        if (point_in_rec(p, rec + rec_off[nbr[k]], -1e-9)) {
-          found = nbr[k];
-          break;
-        }
+  // one round of candidate tests: k-th candidate c(k) for k < kc, test(c) -> accepted
+  auto round = [&](int64_t b, int64_t kc, auto cand, auto test) {
+    const int64_t k = b + lane;
+    int32_t c = -1;
+    bool in = false;
+    if (k < kc) {
+      c = cand(k);
+      in = test(c);
     }
+    if constexpr (WAVE) {
+      const unsigned long long m = __builtin_amdgcn_ballot_w64(in);
+      if (m) found = __shfl(c, (int)__builtin_ctzll(m), 64);
+    } else if (in) {
+      found = c;
+    }
+  };
+  if (h0 >= 0) {
+    const int64_t k0 = nbr_off[h0], kc = nbr_off[h0 + 1] - k0 + 1;  // the previous cell and its neighbours
+    auto cand = [&](int64_t k) { return k == 0 ? h0 : nbr[k0 + k - 1]; };
+    if (WAVE && rec32)
+      for (int64_t b = 0; b < kc && found < 0; b += kStep)
+        round(b, kc, cand, [&](int32_t c) { return surely_in_rec32(p, rec32 + (int64_t)kR32 * c); });
+    for (int64_t b = 0; b < kc && found < 0; b += kStep)
+      round(b, kc, cand, [&](int32_t c) { return point_in_rec(p, rec + rec_off[c], -1e-9); });
   }
-  if (found < 0 && finite) {
+  if (found < 0) {
     const double f0 = floor((p[0] - glo0) / gh), f1 = floor((p[1] - glo1) / gh), f2 = floor((p[2] - glo2) / gh);
     if (f0 >= 0 && f1 >= 0 && f2 >= 0 && f0 < (double)nb0 && f1 < (double)nb1 && f2 < (double)nb2) {
-      const int64_t b = (int64_t)f0 + nb0 * ((int64_t)f1 + nb1 * (int64_t)f2);
-      for (int64_t k = gb_off[b]; k < gb_off[b + 1]; ++k) {
-        const int32_t c = gb_cell[k];
-        const double *B = bb + 6 * (int64_t)c;
-        if (p[0] < B[0] || p[1] < B[1] || p[2] < B[2] || p[0] > B[3] || p[1] > B[4] || p[2] > B[5]) continue;
-        if (point_in_rec(p, rec + rec_off[c], 1e-12)) {
-          found = c;
-          break;
-        }
-      }
+      const int64_t bin = (int64_t)f0 + nb0 * ((int64_t)f1 + nb1 * (int64_t)f2);
+      const int64_t g0 = gb_off[bin], g1 = gb_off[bin + 1];
+      for (int64_t b = 0; b < g1 - g0 && found < 0; b += kStep)
+        round(b, g1 - g0, [&](int64_t k) { return gb_cell[g0 + k]; }, [&](int32_t c) {
+          const double *B = bb + 6 * (int64_t)c;
+          if (p[0] < B[0] || p[1] < B[1] || p[2] < B[2] || p[0] > B[3] || p[1] > B[4] || p[2] > B[5]) return false;
+          return point_in_rec(p, rec + rec_off[c], 1e-12);
+        });
     }
   }
-  cell_t[t] = found;
-  ref[i] = make_float4(0.f, 0.f, 0.f, 0.f);  // no ball until the next record test in this cell
-  if (found < 0)
-    atomicAdd(status, 1ull);
-  else
-    rank_t[t] = atomicAdd(&count[found], 1);
+  return found;
 }
 
-template <typename PT>
-__global__ void k_locate_slow(const PT *__restrict__ pos, const unsigned long long *__restrict__ nslow,
-                              const int32_t *__restrict__ slow, const int32_t *__restrict__ trav,
-                              const int32_t *__restrict__ hint, const int64_t *__restrict__ rec_off,
-                              const double *__restrict__ rec, const int64_t *__restrict__ nbr_off,
-                              const int32_t *__restrict__ nbr, const double *__restrict__ bb,
-                              const int64_t *__restrict__ gb_off, const int32_t *__restrict__ gb_cell, double glo0,
-                              double glo1, double glo2, double gh, int64_t nb0, int64_t nb1, int64_t nb2,
-                              float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ rank_t,
-                              int32_t *__restrict__ count, unsigned long long *__restrict__ status) {
-  // a fixed grid strides over the list, whose length is only known on the device
+// The slow kernel.  WAVE (molecules that have a previous cell): one wave per molecule; otherwise (the first
+// binning, where every molecule comes here) one thread per molecule.  A fixed grid strides over the list,
+// whose length is only known on the device.
+template <typename PT, bool WAVE>
+__global__ __launch_bounds__(256) void k_locate_slow(
+    const PT *__restrict__ pos, const unsigned long long *__restrict__ nslow, const int32_t *__restrict__ slow,
+    const int32_t *__restrict__ trav, const int32_t *__restrict__ hint, const float4 *__restrict__ rec32,
+    const int64_t *__restrict__ rec_off, const double *__restrict__ rec, const int64_t *__restrict__ nbr_off,
+    const int32_t *__restrict__ nbr, const double *__restrict__ bb, const int64_t *__restrict__ gb_off,
+    const int32_t *__restrict__ gb_cell, double glo0, double glo1, double glo2, double gh, int64_t nb0, int64_t nb1,
+    int64_t nb2, float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ rank_t,
+    int32_t *__restrict__ count, unsigned long long *__restrict__ status) {
   const int64_t ns = (int64_t)*nslow;
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < ns; u += (int64_t)gridDim.x * blockDim.x)
-    locate_slow_one<PT>(pos, slow[u], trav, hint, rec_off, rec, nbr_off, nbr, bb, gb_off, gb_cell, glo0, glo1, glo2,
-                        gh, nb0, nb1, nb2, ref, cell_t, rank_t, count, status);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gsize = (int64_t)gridDim.x * blockDim.x;
+  const int64_t u0 = WAVE ? gid >> 6 : gid, ustep = WAVE ? gsize >> 6 : gsize;
+  for (int64_t u = u0; u < ns; u += ustep) {  // wave-uniform with WAVE
+    const int64_t t = slow[u];
+    const int64_t i = trav ? trav[t] : t;
+    const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
+    int32_t found = -1;
+    if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))
+      found = slow_find<WAVE>(p, hint ? hint[t] : -1, rec32, rec_off, rec, nbr_off, nbr, bb, gb_off, gb_cell, glo0,
+                              glo1, glo2, gh, nb0, nb1, nb2);
+    if (!WAVE || (threadIdx.x & 63) == 0) {
+      cell_t[t] = found;
+      ref[i] = make_float4(0.f, 0.f, 0.f, 0.f);  // no ball until the next record test in this cell
+      if (found < 0)
+        atomicAdd(status, 1ull);
+      else
+        rank_t[t] = atomicAdd(&count[found], 1);
+    }
+  }
 }
 
 
@@ -1186,8 +1214,10 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256 * kLocPerLane)), dim3(256), 0, st, (const PT *)pos_dev, \
                      n, trav, hint, r32, h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_rank.as<int32_t>(), \
                      h->d_count.as<int32_t>(), nslow, slow, routes);                                               \
-  hipLaunchKernelGGL((k_locate_slow<PT>), dim3(std::min<int64_t>(grid1d(n, 128), 2048)), dim3(128), 0, st, (const PT *)pos_dev, nslow, slow, \
-                     trav, hint, h->d_rec_off.as<int64_t>(), h->d_rec.as<double>(), h->d_nbr_off.as<int64_t>(),   \
+  hipLaunchKernelGGL(prev ? (k_locate_slow<PT, true>) : (k_locate_slow<PT, false>),                              \
+                     dim3(std::min<int64_t>(prev ? grid1d(n, 4) : grid1d(n, 256), 2048)), dim3(256), 0, st,        \
+                     (const PT *)pos_dev, nslow, slow, trav, hint, r32, h->d_rec_off.as<int64_t>(),              \
+                     h->d_rec.as<double>(), h->d_nbr_off.as<int64_t>(),                                            \
                      h->d_nbr.as<int32_t>(), h->d_bb.as<double>(), h->d_gb_off.as<int64_t>(),                       \
                      h->d_gb_cell.as<int32_t>(), h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1],      \
                      h->gnb[2], h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_rank.as<int32_t>(),       \
