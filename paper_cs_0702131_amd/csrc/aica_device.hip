@@ -88,6 +88,7 @@ struct Timer {
 struct aica_dil {
   Geometry geo;
   std::vector<int32_t> order, rank;
+  std::vector<uint8_t> split_depth;  // k-d tree of the sorted order (groups are its subtrees)
   std::vector<CellPair> pairs;
   double rcut = 0, guard = 0, build_seconds = 0, group_seconds = 0;
   int device = 0;
@@ -1044,9 +1045,9 @@ static int ensure_groups(aica_dil *h, int64_t n) {
   if (h->groups_ready && h->groups_for_n == n) return AICA_OK;
   auto t0 = std::chrono::steady_clock::now();
   const double density = (double)n / h->geo.total_volume;
-  double target = 27.0;  // expected molecules per group (measured best on the channel)
+  double target = 64.0;  // largest expected occupancy of a group (k-d subtree; measured best on the channel)
   if (const char *e = getenv("AICA_GROUP_TARGET")) target = std::max(1.0, atof(e));
-  int rc = build_groups(h->geo, h->order, h->pairs, density, target, h->grp);
+  int rc = build_groups(h->geo, h->order, h->split_depth, h->pairs, density, target, h->grp);
   if (rc) return rc;
   const Groups &G = h->grp;
   const int64_t E = G.e_off[G.ng];
@@ -1131,7 +1132,7 @@ int aica_build_dil_ex(const aica_mesh *mesh, double rcut, double guard, int32_t 
   h->guard = guard;
   const bool verbose = getenv("AICA_VERBOSE") != nullptr;
   auto t1 = std::chrono::steady_clock::now();
-  spatial_order(h->geo, h->order, h->rank);
+  spatial_order(h->geo, h->order, h->rank, h->split_depth);
   auto t2 = std::chrono::steady_clock::now();
   rc = build_cell_pairs(h->geo, h->order, h->rank, rcut + guard, predicate, h->pairs);
   if (verbose)

@@ -93,7 +93,8 @@ int build_geometry(const aica_mesh *m, Geometry &g);
 
 // Spatially coherent cell order (k-d median splits of cell centroids):
 // order[s] = mesh cell at sorted position s; rank[c] = sorted position of mesh cell c.
-void spatial_order(const Geometry &g, std::vector<int32_t> &order, std::vector<int32_t> &rank);
+void spatial_order(const Geometry &g, std::vector<int32_t> &order, std::vector<int32_t> &rank,
+                   std::vector<uint8_t> &split_depth);
 
 // Image n of the periodic directions: T_1^n0 T_2^n1 T_3^n2 (the transforms commute).
 Xf image_transform(const Geometry &g, int n0, int n1, int n2);
@@ -132,7 +133,7 @@ struct Groups {
   std::vector<int32_t> rc_e;
 };
 
-int build_groups(const Geometry &g, const std::vector<int32_t> &order, const std::vector<CellPair> &pairs,
-                 double density, double target, Groups &out);
+int build_groups(const Geometry &g, const std::vector<int32_t> &order, const std::vector<uint8_t> &split_depth,
+                 const std::vector<CellPair> &pairs, double density, double target, Groups &out);
 
 }  // namespace aica

@@ -336,13 +336,18 @@ int build_geometry(const aica_mesh *m, Geometry &g) {
 
 // ------------------------------------------------------------------ spatial order
 
-void spatial_order(const Geometry &g, std::vector<int32_t> &order, std::vector<int32_t> &rank) {
+void spatial_order(const Geometry &g, std::vector<int32_t> &order, std::vector<int32_t> &rank,
+                   std::vector<uint8_t> &split_depth) {
   order.resize(g.nc);
   std::iota(order.begin(), order.end(), 0);
+  // split_depth[s]: depth of the node of the k-d tree that splits its range at sorted position s (every
+  // position but 0 splits exactly one node; the root has depth 0)
+  split_depth.assign(g.nc, 255);
   struct Range {
     int64_t b, e;
+    int depth;
   };
-  std::vector<Range> stack{{0, g.nc}};
+  std::vector<Range> stack{{0, g.nc, 0}};
   while (!stack.empty()) {
     Range r = stack.back();
     stack.pop_back();
@@ -362,9 +367,10 @@ void spatial_order(const Geometry &g, std::vector<int32_t> &order, std::vector<i
       double va = g.ccen[3 * (int64_t)a + ax], vb = g.ccen[3 * (int64_t)b + ax];
       return va < vb || (va == vb && a < b);
     });
+    split_depth[mid] = (uint8_t)std::min(r.depth, 254);
     // right half pushed first so the left half is processed (and ordered) first
-    stack.push_back({mid, r.e});
-    stack.push_back({r.b, mid});
+    stack.push_back({mid, r.e, r.depth + 1});
+    stack.push_back({r.b, mid, r.depth + 1});
   }
   rank.assign(g.nc, 0);
   for (int64_t s = 0; s < g.nc; ++s) rank[order[s]] = (int32_t)s;
@@ -803,22 +809,38 @@ int build_cell_pairs(const Geometry &g, const std::vector<int32_t> &order, const
 
 // ------------------------------------------------------------------ interaction groups
 
-int build_groups(const Geometry &g, const std::vector<int32_t> &order, const std::vector<CellPair> &pairs,
-                 double density, double target, Groups &G) {
+int build_groups(const Geometry &g, const std::vector<int32_t> &order, const std::vector<uint8_t> &split_depth,
+                 const std::vector<CellPair> &pairs, double density, double target, Groups &G) {
   const int64_t nc = g.nc;
   G.cell0.clear();
   G.of_cell.assign(nc, 0);
-  // greedy packing along the sorted order to an expected occupancy target
-  double acc = 0;
-  G.cell0.push_back(0);
-  for (int64_t s = 0; s < nc; ++s) {
-    double e = density * g.vol[order[s]];
-    if (s > G.cell0.back() && acc + e > target) {
-      G.cell0.push_back((int32_t)s);
-      acc = 0;
+  // Groups are subtrees of the k-d tree of the sorted order: descending from the root, a subtree whose
+  // expected occupancy is at most the target becomes a group, so every group is a compact box-like block
+  // of cells (a run of the sorted order cut at arbitrary places would straddle subtrees and spread out).
+  std::vector<double> vpre(nc + 1, 0.0);
+  for (int64_t s = 0; s < nc; ++s) vpre[s + 1] = vpre[s] + g.vol[order[s]];
+  struct Node {
+    int64_t b, e;
+    int depth;
+  };
+  std::vector<Node> stack{{0, nc, 0}};
+  while (!stack.empty()) {
+    const Node r = stack.back();
+    stack.pop_back();
+    if (r.e <= r.b) continue;
+    if (r.e - r.b == 1 || density * (vpre[r.e] - vpre[r.b]) <= target) {
+      G.cell0.push_back((int32_t)r.b);
+      continue;
     }
-    acc += e;
-    G.of_cell[s] = (int32_t)(G.cell0.size() - 1);
+    int64_t mid = r.b + 1;
+    while (mid < r.e && split_depth[mid] != (uint8_t)std::min(r.depth, 254)) ++mid;
+    if (mid >= r.e) mid = r.b + (r.e - r.b) / 2;  // (not reached: every inner node has its split)
+    stack.push_back({mid, r.e, r.depth + 1});
+    stack.push_back({r.b, mid, r.depth + 1});
+  }
+  for (size_t k = 0; k < G.cell0.size(); ++k) {
+    const int64_t e = k + 1 < G.cell0.size() ? G.cell0[k + 1] : nc;
+    for (int64_t s = G.cell0[k]; s < e; ++s) G.of_cell[s] = (int32_t)k;
   }
   G.cell0.push_back((int32_t)nc);
   G.ng = (int64_t)G.cell0.size() - 1;
