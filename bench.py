@@ -69,25 +69,30 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the copy-kernel calibration), or None when
-    the summary is missing or was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+COUNTERS_FILE = "counters_pair_{workload}_fp32.txt"
+
+
+def measured_counters(kernel, workload):
+    """Per-launch figures of a pair kernel ("pair_fwd" / "pair_adj") from the committed counter summary of
+    `workload`: HBM traffic in bytes (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel calibration),
+    VALU issue as a fraction of the chip's issue peak, and executed VALU FLOPs.  Empty when the summary is
+    missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", COUNTERS_FILE.format(workload=workload))
     if not os.path.exists(path):
-        return None
-    rows = {}
-    digest = None
+        return {}
+    out, digest = {}, None
     with open(path) as fh:
         for line in fh:
             f = line.split()
             if len(f) >= 2 and f[0] == "sources_sha256:":
                 digest = f[1]
-            if len(f) == 6 and f[0] == "traffic:":
-                rows[f[1]] = float(f[2]) * 1024 * float(f[3]) + float(f[4]) * 1024 * float(f[5])
-    if digest != kernel_digest():
-        return None
-    return rows.get(kernel)
+            elif len(f) == 6 and f[0] == "traffic:" and f[1] == kernel:
+                out["traffic"] = float(f[2]) * 1024 * float(f[3]) + float(f[4]) * 1024 * float(f[5])
+            elif len(f) == 3 and f[0] == "issue:" and f[1] == kernel:
+                out["valu_issue_frac"] = float(f[2])
+            elif len(f) == 3 and f[0] == "flops:" and f[1] == kernel:
+                out["executed_flop"] = float(f[2])
+    return out if digest == kernel_digest() else {}
 
 
 PAIR_KERNELS = {"pair_fwd": "k_pair<float, 0, 0, true, false>", "pair_adj": "k_pair_adj<float, 0, false>"}
@@ -121,23 +126,6 @@ def moving_sets(wl, count, step=0.005, seed=11):
             x[:, a] = np.clip(x[:, a], lo[a], hi[a])
         sets.append(x)
     return sets
-
-
-def measured_valu_issue(kernel, workload):
-    """Executed VALU instructions of `kernel` over its launch duration as a fraction of the chip's VALU issue
-    peak, from the committed counter summary, or None when it is missing or was taken on other kernel
-    sources."""
-    path = os.path.join(ROOT, "profiles", f"valu_{workload}.txt")
-    if not os.path.exists(path) or kernel not in PAIR_KERNELS:
-        return None
-    digest, frac = None, None
-    with open(path) as fh:
-        for line in fh:
-            if line.startswith("# kernel sources sha256"):
-                digest = line.split(":")[-1].strip()
-            elif line.strip().startswith(PAIR_KERNELS[kernel]):
-                frac = float(line.split()[-1])
-    return frac if digest == kernel_digest() else None
 
 
 def timed_steps(A, d, xs, sp, wl, G, precision, steps, warmup, adjoint=True):
@@ -243,6 +231,88 @@ def cpu_baseline(wl, seconds_target, F32, F64, G, gx32, gx64, rng_seed=7):
             "errors": errs}
 
 
+VALU_ISSUE_PEAK = 256 * 2.4e9  # one 64-lane VALU instruction per CU per cycle
+
+
+def pmc_summary(paths, calib_fetch=None, calib_write=None, calib_mib=512):
+    """Summarise rocprofv3 --pmc counter CSVs (run_counter_collection.csv): per kernel the dispatch count,
+    mean duration under counters and the mean of every counter per dispatch; then, for the pair kernels,
+    the lines the benchmark reads: VALU issue fraction (SQ_INSTS_VALU over the duration against one
+    instruction per CU per cycle), executed FLOPs (64 lanes x the FLOPS_FP32/_FP64 counters and their
+    transcendental parts, which count per wave instruction) and HBM traffic (FETCH_SIZE and WRITE_SIZE in
+    KiB with the scale of the same counter on a device copy of known size)."""
+    import csv
+    import re
+    def load(path):
+        acc, dur = {}, {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                k = re.sub(r"\(.*", "", r["Kernel_Name"].replace("void (anonymous namespace)::", "")
+                           .replace("(anonymous namespace)::", ""))
+                acc.setdefault(k, {}).setdefault(r["Counter_Name"], {})[r["Dispatch_Id"]] = (
+                    acc.get(k, {}).get(r["Counter_Name"], {}).get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"]))
+                dur.setdefault(k, {})[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+        return acc, dur
+    acc, dur = {}, {}
+    for p in paths:
+        a, d = load(p)
+        for k in a:
+            for c, v in a[k].items():
+                acc.setdefault(k, {})[c] = v
+            dur.setdefault(k, {}).update({(p, i): t for i, t in d[k].items()})
+    mean = {k: {c: sum(v.values()) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+    scale = {}
+    for name, path in (("FETCH_SIZE", calib_fetch), ("WRITE_SIZE", calib_write)):
+        if path:
+            a, _ = load(path)
+            vals = [sum(v.values()) / len(v) for k, cs in a.items() if "copyBuffer" in k for c, v in cs.items()
+                    if c == name]
+            nbytes = float(calib_mib) * (1 << 20)
+            scale[name] = nbytes / 1024 / vals[0] if vals else None
+    names = sorted({c for cs in mean.values() for c in cs})
+    short = [n.replace("SQ_INSTS_VALU_", "").replace("SQ_INSTS_", "").replace("SQ_", "") for n in names]
+    lines = ["# counter columns: " + ", ".join(names),
+             f"# {'kernel':40s} {'ms(pmc)':>8s} " + " ".join(f"{n[:11]:>11s}" for n in short)]
+    for k in sorted(mean, key=lambda k: -sum(dur[k].values()) / len(dur[k])):
+        ms = 1e3 * sum(dur[k].values()) / len(dur[k])
+        if ms < 0.01:
+            continue
+        lines.append(f"# {k[:40]:40s} {ms:8.3f} " + " ".join(f"{mean[k].get(n, 0.0):11.4e}" for n in names))
+    for key, kern in PAIR_KERNELS.items():
+        if kern not in mean:
+            continue
+        m, t = mean[kern], sum(dur[kern].values()) / len(dur[kern])
+        if "SQ_INSTS_VALU" in m:
+            lines.append(f"issue: {key} {m['SQ_INSTS_VALU'] / t / VALU_ISSUE_PEAK:.4f}")
+        fl = [c for c in ("SQ_INSTS_VALU_FLOPS_FP32", "SQ_INSTS_VALU_FLOPS_FP32_TRANS", "SQ_INSTS_VALU_FLOPS_FP64",
+                          "SQ_INSTS_VALU_FLOPS_FP64_TRANS") if c in m]
+        if len(fl) == 4:
+            lines.append(f"flops: {key} {64 * sum(m[c] for c in fl):.6e}")
+        if "FETCH_SIZE" in m and "WRITE_SIZE" in m and scale.get("FETCH_SIZE") and scale.get("WRITE_SIZE"):
+            lines.append(f"traffic: {key} {m['FETCH_SIZE']:.1f} {scale['FETCH_SIZE']:.4f} {m['WRITE_SIZE']:.1f} "
+                         f"{scale['WRITE_SIZE']:.4f}")
+    lines.append(f"sources_sha256: {kernel_digest()}")
+    return "\n".join(lines)
+
+
+def trace_summary(path):
+    """Summarise a rocprofv3 --kernel-trace --stats run_kernel_stats.csv: per kernel the calls and the mean,
+    smallest and largest duration (microseconds) and the share of the total kernel time."""
+    import csv
+    import re
+    lines = [f"# {'kernel':46s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            k = re.sub(r"\(.*", "", r["Name"].replace("void (anonymous namespace)::", "")
+                       .replace("(anonymous namespace)::", ""))
+            if float(r["Percentage"]) < 0.05:
+                continue
+            lines.append(f"  {k[:46]:46s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.1f} "
+                         f"{float(r['MinNs']) / 1e3:10.1f} {float(r['MaxNs']) / 1e3:10.1f} {float(r['Percentage']):6.2f}")
+    lines.append(f"# kernel sources sha256 (first 16 hex): {kernel_digest()}")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,7 +325,20 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates the FETCH_SIZE and "
                          "WRITE_SIZE counters against a kernel of known traffic) and exit")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
+                    help="only summarise rocprofv3 --pmc output (run_counter_collection.csv files) and exit")
+    ap.add_argument("--calib-fetch", metavar="CSV", help="with --pmc-summary: FETCH_SIZE run of --copy-calibration")
+    ap.add_argument("--calib-write", metavar="CSV", help="with --pmc-summary: WRITE_SIZE run of --copy-calibration")
+    ap.add_argument("--calib-mib", type=int, default=512, help="with --pmc-summary: MiB of the calibration copy")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="only summarise a rocprofv3 --kernel-trace --stats run_kernel_stats.csv and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return
+    if args.pmc_summary:
+        print(pmc_summary(args.pmc_summary, args.calib_fetch, args.calib_write, args.calib_mib))
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4
@@ -340,10 +423,13 @@ def main():
     else:
         kname, kms, flops = "pair_fwd", fwd_ms, FLOP_FWD_PAIR * npairs + FLOP_REJECT * rejected
     achieved = flops / (kms * 1e-3) / 1e12
-    traffic = measured_traffic(kname, args.workload)
+    ctr = measured_counters(kname, args.workload)
+    ex = ctr.get("executed_flop")
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic, "traffic_unit": "bytes per launch",
-                "valu_issue_frac": measured_valu_issue(kname, args.workload),
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": ctr.get("traffic"), "traffic_unit": "bytes per launch",
+                "valu_issue_frac": ctr.get("valu_issue_frac"),
+                "executed_tflops": None if ex is None else ex / (kms * 1e-3) / 1e12,
+                "executed_frac": None if ex is None else ex / (kms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
                 "kernel": kname,
                 "kernel_ms": kms, "algorithmic_flop": flops}
 

@@ -96,6 +96,7 @@ struct aica_dil {
   // device geometry for point location (mesh cell ids)
   DBuf d_rec_off, d_rec, d_bb;  // point-location cell records and padded boxes, sorted cell order
   DBuf d_rec32;                 // FP32 records for the previous-cell test (cells of at most kR32 float4)
+  DBuf d_pl32;                  // plane records of the boundary triangles (kPl float4 per cell, with d_rec32)
   DBuf d_nbr_off, d_nbr;        // cells across each cell's interior faces (sorted ids)
   bool has_rec32 = false;
   DBuf d_gb_off, d_gb_cell;
@@ -306,6 +307,39 @@ __device__ float4 inner_ball(const double *p, const float4 *R) {
   return make_float4(pc[0], pc[1], pc[2], r > 0 ? (float)r : 0.f);
 }
 
+// Plane records: per sorted cell kPl float4 (n, d), one per boundary triangle of the cell's face fans: the
+// inward unit normal n and d = n.(f - a) for a point f of the triangle, in the frame a of the cell's FP32
+// record, so that n.(p - a) - d is the signed distance of p from the triangle's plane (positive inside).
+// Unused entries are (0, 0, 0, -3e38); a cell with more triangles than kPl has (0, 0, 0, 3e38) in entry 0,
+// so that its test never accepts.
+constexpr int kPl = 24;
+
+// A point on the inner side of every boundary triangle's plane is strictly inside the cell: from a point
+// outside the cell (or on its boundary), a segment to an interior point enters the cell through some
+// boundary triangle, so that point lies on the outer side of (or on) the triangle's plane.  Accepts p when
+// the smallest signed distance exceeds 1e-4 of the cell's size (the FP32 rounding of the planes, of p - a
+// and of the sums is below 1e-6 of it), and gives the ball about p (centre rounded to FP32) that stays
+// inside: radius = that distance less the margin and the centre's rounding.  A point inside but not this
+// far from every plane (near the boundary, or beside a reflex crease of a non-convex cell) is left to the
+// fan test.
+__device__ bool plane_ball(const double *p, const float4 *R, const float4 *PL, float4 &ball) {
+  const float4 h = R[0];
+  const float size = R[1].w;
+  const float pr0 = (float)(p[0] - (double)h.y), pr1 = (float)(p[1] - (double)h.z), pr2 = (float)(p[2] - (double)h.w);
+  float smin = 3.0e38f;
+#pragma unroll 8
+  for (int k = 0; k < kPl; ++k) {
+    const float4 q = PL[k];
+    smin = fminf(smin, fmaf(q.x, pr0, fmaf(q.y, pr1, fmaf(q.z, pr2, -q.w))));
+  }
+  if (!(smin > 1e-4f * size)) return false;
+  const float pc[3] = {(float)p[0], (float)p[1], (float)p[2]};
+  const double s0 = p[0] - (double)pc[0], s1 = p[1] - (double)pc[1], s2 = p[2] - (double)pc[2];
+  const double r = (double)smin * (1.0 - 1e-6) - 1e-4 * (double)size - sqrt(s0 * s0 + s1 * s1 + s2 * s2);
+  ball = make_float4(pc[0], pc[1], pc[2], r > 0 ? (float)r : 0.f);
+  return true;
+}
+
 // Locate each molecule: cell_of[i] = sorted index of the cell that contains x_i, in two kernels so that
 // the rare slow cases do not hold up whole waves.
 // k_locate_fast visits molecules in the order trav (the previous binning's sorted order, so that
@@ -329,9 +363,9 @@ constexpr int kLocPerLane = 4;  // molecules per lane in the fast kernel
 template <typename PT>
 __global__ __launch_bounds__(256) void k_locate_fast(
     const PT *__restrict__ pos, int64_t n, const int32_t *__restrict__ trav, const int32_t *__restrict__ hint,
-    const float4 *__restrict__ rec32, float4 *__restrict__ ref, int32_t *__restrict__ cell_t,
-    int32_t *__restrict__ rank_t, int32_t *__restrict__ count, unsigned long long *__restrict__ nslow,
-    int32_t *__restrict__ slow, unsigned long long *__restrict__ routes) {
+    const float4 *__restrict__ rec32, const float4 *__restrict__ pl32, float4 *__restrict__ ref,
+    int32_t *__restrict__ cell_t, int32_t *__restrict__ rank_t, int32_t *__restrict__ count,
+    unsigned long long *__restrict__ nslow, int32_t *__restrict__ slow, unsigned long long *__restrict__ routes) {
   constexpr int kSpan = 64 * kLocPerLane;  // molecules per wave
   __shared__ int32_t rec_l[4][kSpan];      // per wave: slots (relative to the wave's first) for the records
   __shared__ int32_t slow_l[4][kSpan];     // per wave: slots for the slow kernel
@@ -383,14 +417,24 @@ __global__ __launch_bounds__(256) void k_locate_fast(
       const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
       const int32_t h0 = hint[t];
       int32_t found = -1, across = -1;
-      if (surely_in_rec32(p, rec32 + (int64_t)kR32 * h0, &across)) {
+      float4 ball;
+      bool have_ball = false;  // the plane test accepted and gave the ball
+      if (pl32 && plane_ball(p, rec32 + (int64_t)kR32 * h0, pl32 + (int64_t)kPl * h0, ball)) {
         found = h0;
-      } else if (across >= 0 && surely_in_rec32(p, rec32 + (int64_t)kR32 * across)) {
-        found = across;
+        have_ball = true;
+      } else if (surely_in_rec32(p, rec32 + (int64_t)kR32 * h0, &across)) {
+        found = h0;
+      } else if (across >= 0) {
+        if (pl32 && plane_ball(p, rec32 + (int64_t)kR32 * across, pl32 + (int64_t)kPl * across, ball)) {
+          found = across;
+          have_ball = true;
+        } else if (surely_in_rec32(p, rec32 + (int64_t)kR32 * across)) {
+          found = across;
+        }
       }
       if (found >= 0) {
         how = 1;
-        ref[i] = inner_ball(p, rec32 + (int64_t)kR32 * found);
+        ref[i] = have_ball ? ball : inner_ball(p, rec32 + (int64_t)kR32 * found);
         cell_t[t] = found;
         rank_t[t] = atomicAdd(&count[found], 1);
       } else {
@@ -478,7 +522,8 @@ template <typename PT, bool WAVE>
 __global__ __launch_bounds__(256) void k_locate_slow(
     const PT *__restrict__ pos, const unsigned long long *__restrict__ nslow, const int32_t *__restrict__ slow,
     const int32_t *__restrict__ trav, const int32_t *__restrict__ hint, const float4 *__restrict__ rec32,
-    const int64_t *__restrict__ rec_off, const double *__restrict__ rec, const int64_t *__restrict__ nbr_off,
+    const float4 *__restrict__ pl32, const int64_t *__restrict__ rec_off, const double *__restrict__ rec,
+    const int64_t *__restrict__ nbr_off,
     const int32_t *__restrict__ nbr, const double *__restrict__ bb, const int64_t *__restrict__ gb_off,
     const int32_t *__restrict__ gb_cell, double glo0, double glo1, double glo2, double gh, int64_t nb0, int64_t nb1,
     int64_t nb2, float4 *__restrict__ ref, int32_t *__restrict__ cell_t, int32_t *__restrict__ rank_t,
@@ -496,7 +541,14 @@ __global__ __launch_bounds__(256) void k_locate_slow(
                               glo1, glo2, gh, nb0, nb1, nb2);
     if (!WAVE || (threadIdx.x & 63) == 0) {
       cell_t[t] = found;
-      ref[i] = make_float4(0.f, 0.f, 0.f, 0.f);  // no ball until the next record test in this cell
+      // the ball about p inside the cell found, when the plane test shows p that far inside; else no ball
+      // until the next record test in this cell
+      float4 ball = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (found >= 0 && pl32) {
+        float4 b;
+        if (plane_ball(p, rec32 + (int64_t)kR32 * found, pl32 + (int64_t)kPl * found, b)) ball = b;
+      }
+      ref[i] = ball;
       if (found < 0)
         atomicAdd(status, 1ull);
       else
@@ -933,16 +985,49 @@ static int upload_geometry(aica_dil *h) {
     }
     h->has_rec32 = fits;
     if (fits) {
-      std::vector<float4> r32((size_t)g.nc * kR32);
+      std::vector<float4> r32((size_t)g.nc * kR32), pl32((size_t)g.nc * kPl);
       parallel_for(g.nc, [&](int64_t s0, int64_t s1, int) {
         for (int64_t s = s0; s < s1; ++s) {
           const double *R = rec.data() + roff[s];
           const int64_t nf = (int64_t)R[0];
           float4 *O = r32.data() + (size_t)s * kR32;
           const double a[3] = {(double)(float)R[1], (double)(float)R[2], (double)(float)R[3]};
-          O[0] = make_float4((float)nf, (float)a[0], (float)a[1], (float)a[2]);
-          O[1] = make_float4((float)(R[1] - a[0]), (float)(R[2] - a[1]), (float)(R[3] - a[2]), 0.f);
           const double *FC = R + 4, *LEN = FC + 3 * nf, *V = LEN + nf;
+          // the cell's size: the largest distance from the vertex mean to a face centroid
+          double size = 0;
+          for (int64_t k = 0; k < nf; ++k) {
+            const double e0 = FC[3 * k] - R[1], e1 = FC[3 * k + 1] - R[2], e2 = FC[3 * k + 2] - R[3];
+            size = std::max(size, std::sqrt(e0 * e0 + e1 * e1 + e2 * e2));
+          }
+          O[0] = make_float4((float)nf, (float)a[0], (float)a[1], (float)a[2]);
+          O[1] = make_float4((float)(R[1] - a[0]), (float)(R[2] - a[1]), (float)(R[3] - a[2]), (float)size);
+          // plane records (layout at plane_ball): the face loops run with the right-hand normal out of the cell
+          float4 *PL = pl32.data() + (size_t)s * kPl;
+          for (int k = 0; k < kPl; ++k) PL[k] = make_float4(0.f, 0.f, 0.f, -3.0e38f);
+          {
+            int ntri = 0;
+            const double *Vk = V;
+            for (int64_t k = 0; k < nf; ++k) {
+              const int64_t len = (int64_t)LEN[k];
+              const double *f = FC + 3 * k;
+              for (int64_t j = 0; j < len; ++j) {
+                const double *v0 = Vk + 3 * j, *v1 = Vk + 3 * ((j + 1) % len);
+                const double u[3] = {v0[0] - f[0], v0[1] - f[1], v0[2] - f[2]};
+                const double w[3] = {v1[0] - f[0], v1[1] - f[1], v1[2] - f[2]};
+                double nrm[3] = {-(u[1] * w[2] - u[2] * w[1]), -(u[2] * w[0] - u[0] * w[2]), -(u[0] * w[1] - u[1] * w[0])};
+                const double nn = std::sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
+                if (ntri < kPl && nn > 0) {
+                  for (int q = 0; q < 3; ++q) nrm[q] /= nn;
+                  const double dd = nrm[0] * (f[0] - a[0]) + nrm[1] * (f[1] - a[1]) + nrm[2] * (f[2] - a[2]);
+                  PL[ntri] = make_float4((float)nrm[0], (float)nrm[1], (float)nrm[2], (float)dd);
+                }
+                if (!(nn > 0)) ntri = kPl;  // a degenerate triangle: no plane test for this cell
+                ++ntri;
+              }
+              Vk += 3 * len;
+            }
+            if (ntri > kPl) PL[0] = make_float4(0.f, 0.f, 0.f, 3.0e38f);
+          }
           int64_t nv = 0;
           for (int64_t k = 0; k < nf; ++k) {
             O[2 + k] = make_float4((float)(FC[3 * k] - a[0]), (float)(FC[3 * k + 1] - a[1]), (float)(FC[3 * k + 2] - a[2]),
@@ -964,6 +1049,7 @@ static int upload_geometry(aica_dil *h) {
         }
       });
       if ((rc = upload(h->d_rec32, r32))) return rc;
+      if ((rc = upload(h->d_pl32, pl32))) return rc;
     }
   }
   // cells across each cell's interior faces, sorted ids in sorted cell order
@@ -1209,15 +1295,16 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
   const int32_t *hint = prev ? h->d_cell_sorted.as<int32_t>() : nullptr;
   if (n > 0) {
     const float4 *r32 = h->has_rec32 ? h->d_rec32.as<float4>() : nullptr;
+    const float4 *pl = h->has_rec32 ? h->d_pl32.as<float4>() : nullptr;
     int32_t *slow = h->d_slow.as<int32_t>();
     unsigned long long *nslow = status + 2;
 #define AICA_LOCATE(PT)                                                                                            \
   hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256 * kLocPerLane)), dim3(256), 0, st, (const PT *)pos_dev, \
-                     n, trav, hint, r32, h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_rank.as<int32_t>(), \
+                     n, trav, hint, r32, pl, h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_rank.as<int32_t>(), \
                      h->d_count.as<int32_t>(), nslow, slow, routes);                                               \
   hipLaunchKernelGGL(prev ? (k_locate_slow<PT, true>) : (k_locate_slow<PT, false>),                              \
                      dim3(std::min<int64_t>(prev ? grid1d(n, 4) : grid1d(n, 256), 2048)), dim3(256), 0, st,        \
-                     (const PT *)pos_dev, nslow, slow, trav, hint, r32, h->d_rec_off.as<int64_t>(),              \
+                     (const PT *)pos_dev, nslow, slow, trav, hint, r32, pl, h->d_rec_off.as<int64_t>(),          \
                      h->d_rec.as<double>(), h->d_nbr_off.as<int64_t>(),                                            \
                      h->d_nbr.as<int32_t>(), h->d_bb.as<double>(), h->d_gb_off.as<int64_t>(),                       \
                      h->d_gb_cell.as<int32_t>(), h->glo[0], h->glo[1], h->glo[2], h->gh, h->gnb[0], h->gnb[1],      \
@@ -1310,7 +1397,9 @@ struct ForceWs {
 // Reaction buffer: (re)allocate, fill with a pattern no epoch can equal, and advance the epoch.
 static int prepare_jpart(aica_dil *h, size_t bytes, hipStream_t st) {
   const void *old = h->d_jpart.p;
-  int rc = h->d_jpart.ensure(bytes);
+  // a growing buffer gets 1/8 headroom: the slot count follows the occupancy of every step, and each
+  // reallocation costs a fill of the whole buffer
+  int rc = h->d_jpart.ensure(bytes > h->d_jpart.bytes ? bytes + bytes / 8 : bytes);
   if (rc) return rc;
   if (h->d_jpart.p != old || h->jpart_tagged < h->d_jpart.bytes || h->epoch >= kMaxEpoch) {
     const int64_t words = (int64_t)(h->d_jpart.bytes / 4);

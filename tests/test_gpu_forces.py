@@ -366,10 +366,11 @@ def test_binning_ties_on_faces_edges_vertices(A, oracle):
 
 
 def test_binning_balls_and_routes(A, oracle):
-    """Tracking (the paper's membership kept from step to step): the first binning searches, the second
-    tests every molecule against its previous cell's record and keeps a ball inside that cell, the third
-    (same positions) needs no geometry at all; small moves then mix the routes, and a molecule that crossed
-    a face is mostly located by the record of the cell across it.  Every binning equals brute-force
+    """Tracking (the paper's membership kept from step to step): the first binning searches and gives each
+    molecule that the plane test shows well inside its cell a ball inside that cell; the second finds those
+    in their balls and tests the rest against their previous cell's record (which keeps a ball too); the
+    third (same positions) needs no geometry at all; small moves then mix the routes, and a molecule that
+    crossed a face is mostly located by the record of the cell across it.  Every binning equals brute-force
     location, and the routes add up to n."""
     import torch
     wl = W.small_random(n_mesh=(5, 4, 5), L=(10.0, 8.0, 10.0), N=500, seed=31, mesh_jitter=0.25)
@@ -393,7 +394,7 @@ def test_binning_balls_and_routes(A, oracle):
         assert sum(r) == len(x), (step, r)
     _note(f"routes (ball, record, search) per binning: {routes}")
     assert routes[0] == (0, 0, len(x))
-    assert routes[1][0] == 0 and routes[1][1] >= 0.95 * len(x)
+    assert routes[1][0] >= 0.5 * len(x) and routes[1][0] + routes[1][1] >= 0.95 * len(x)
     assert routes[2][0] >= 0.95 * len(x)
     assert routes[5][0] > 0 and routes[5][1] + routes[5][2] > 0
     # a molecule that crossed a face is mostly found by the FP32 record of the cell across the face it
