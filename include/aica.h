@@ -180,13 +180,16 @@ int aica_forces_noalloc(aica_dil *dil, const void *pos_dev, const int32_t *speci
  * grad_forces_dev: device [n][3] in the compute dtype (G), caller order.
  * grad_energy: gamma (host scalar).  grad_pos_dev: device [n][3] compute dtype,
  * overwritten.  grad_eps_dev, grad_sigma_dev: device double[n_species],
- * overwritten (either may be NULL).  Same preconditions as aica_forces;
- * params->n_species must be 1 or 2.  Precision: the pair terms (which carry up
+ * overwritten (either may be NULL).  Same preconditions as aica_forces
+ * (1..8 species).  Precision: the pair terms (which carry up
  * to r^-16) are formed in FP64 in both precisions, from the FP32 positions and G
  * with AICA_FP32 (whose differences are exact for multiples of 2^-15), and summed
  * per molecule in FP64; with AICA_FP32 only the roundings of the per-entry
- * partial sums and of the result to FP32 remain.
- * Errors: AICA_E_INVAL (also for more than two species), AICA_E_NOMEM, AICA_E_HIP. */
+ * partial sums and of the result to FP32 remain.  The parameter gradients are
+ * the per species-pair sums of dl/deps_ab and dl/dsigma_ab (FP64) taken back to
+ * the species through the mixing rule (d eps_ab/d eps_a = eps_ab/(2 eps_a) and
+ * d sigma_ab/d sigma_a = 1/2 for a != b).
+ * Errors: AICA_E_INVAL, AICA_E_NOMEM, AICA_E_HIP. */
 int aica_forces_adjoint(aica_dil *dil, const void *pos_dev, const int32_t *species_dev, const aica_params *params,
                         const void *grad_forces_dev, double grad_energy, void *grad_pos_dev, double *grad_eps_dev,
                         double *grad_sigma_dev, void *hip_stream);

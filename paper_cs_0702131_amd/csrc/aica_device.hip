@@ -1458,7 +1458,7 @@ static int launch_pair(aica_dil *h, const ForceWs &ws, const LJTab &tab, bool co
   return AICA_OK;
 }
 
-// The adjoint pair kernel (one or two species).
+// The adjoint pair kernel (one, two, or three to eight species).
 template <typename T>
 static int launch_adj(aica_dil *h, const LJTab &tab, const AdjTab &at, hipStream_t st) {
   using V4 = typename Vec4<T>::type;
@@ -1477,10 +1477,12 @@ static int launch_adj(aica_dil *h, const LJTab &tab, const AdjTab &at, hipStream
                      h->d_own.as<T>(), h->d_gpar.as<double>(), ng, padded, tab, at, rot, evd, h->epoch)
   if (rot) {
     if (tab.nsp == 1) AICA_LAUNCH_ADJ(0, true);
-    else AICA_LAUNCH_ADJ(1, true);
+    else if (tab.nsp == 2) AICA_LAUNCH_ADJ(1, true);
+    else AICA_LAUNCH_ADJ(2, true);
   } else {
     if (tab.nsp == 1) AICA_LAUNCH_ADJ(0, false);
-    else AICA_LAUNCH_ADJ(1, false);
+    else if (tab.nsp == 2) AICA_LAUNCH_ADJ(1, false);
+    else AICA_LAUNCH_ADJ(2, false);
   }
 #undef AICA_LAUNCH_ADJ
   HIPCHK(hipGetLastError());

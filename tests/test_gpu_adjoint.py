@@ -67,6 +67,25 @@ def test_adjoint_vs_oracle(A, oracle, frac):
         assert abs(L - rL) < (1e-12 if prec == "fp64" else 1e-5) * abs(rL)
 
 
+@pytest.mark.parametrize("nsp", [3, 5])
+def test_adjoint_many_species(A, oracle, nsp):
+    """Mixtures of three and five species (the adjoint's general path, whose parameter sums are kept per
+    species pair): dL/dx, dL/deps, dL/dsigma and L against the oracle in both precisions."""
+    wl, G = _case(frac=None)
+    wl.species = np.random.default_rng(40 + nsp).integers(0, nsp, size=wl.n).astype(np.int32)
+    wl.eps, wl.sigma = np.linspace(1.0, 0.5, nsp), np.linspace(1.0, 0.85, nsp)
+    gam = 0.1
+    rx, re, rs, rL = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        gx, ge, gs, L = gpu_adjoint(A, wl, G, gam, prec)
+        ex = rel_max(gx, rx)
+        ee = np.abs(ge - re).max() / np.abs(re).max()
+        es = np.abs(gs - rs).max() / np.abs(rs).max()
+        _note(f"adjoint {prec} species={nsp}: dx {ex:.2e} deps {ee:.2e} dsig {es:.2e}")
+        assert ex < tol and ee < tol and es < tol
+        assert abs(L - rL) < (1e-12 if prec == "fp64" else 1e-5) * abs(rL)
+
+
 def test_adjoint_vs_finite_differences(A, oracle):
     """FP64 central differences (h = 1e-6) of the oracle's L for the four parameters and for
     coordinates whose perturbation leaves the pair set unchanged."""

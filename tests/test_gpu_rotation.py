@@ -200,6 +200,36 @@ def test_wedge_adjoint_vs_oracle(A, oracle):
         d.close()
 
 
+def test_wedge_adjoint_three_species(A, oracle):
+    """Rotating referral with three species (the adjoint's general path with rotated images): dL/dx and the
+    parameter gradients against the oracle in both precisions."""
+    import torch
+    wl = W.wedge(r1=30.0, Lz=12.0, nr=16, nphi=16, nz=10)
+    assert len(_near_cutoff(wl, 1e-5)) == 0
+    wl.species = np.random.default_rng(62).integers(0, 3, size=wl.n).astype(np.int32)
+    wl.eps, wl.sigma = np.array([1.0, 0.6, 0.8]), np.array([1.0, 0.9, 0.95])
+    G = W.qround(np.random.default_rng(63).standard_normal((wl.n, 3)))
+    gam = 0.2
+    rx, re, rs, rL = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.lattice, G, gam,
+                                    rot=wl.rotations)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        d = A.DIL(wl.mesh, wl.rcut)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        x = torch.tensor(wl.x, dtype=dt, device="cuda")
+        sp = torch.tensor(wl.species, dtype=torch.int32, device="cuda")
+        A.aica_bin(d, x)
+        gx, ge, gs = A.aica_forces_adjoint(d, x, torch.tensor(G, dtype=dt, device="cuda"), gam, sp, wl.eps,
+                                           wl.sigma, precision=prec)
+        torch.cuda.synchronize()
+        gx = gx.double().cpu().numpy()
+        ex = np.abs(gx - rx).max() / np.sqrt((rx ** 2).mean())
+        ee = np.abs(ge.cpu().numpy() - re).max() / np.abs(re).max()
+        es = np.abs(gs.cpu().numpy() - rs).max() / np.abs(rs).max()
+        _note(f"  adjoint {prec} three species: dx {ex:.2e} deps {ee:.2e} dsig {es:.2e}")
+        assert ex < tol and ee < tol and es < tol
+        d.close()
+
+
 def test_wedge_nve_angular_momentum(A):
     """Velocity Verlet in the sector (FP64), molecules crossing the coupled sides (wrapped by the
     sector rotation, position and velocity) and z, reflected at the walls.  Every pair force is central

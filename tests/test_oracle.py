@@ -398,6 +398,30 @@ def test_adjoint_parameter_fd(oracle):
     assert abs((wl.eps * ge).sum() - L) < 1e-10 * abs(L)
 
 
+def test_adjoint_parameter_fd_three_species(oracle):
+    """Three species under Lorentz-Berthelot: the oracle's parameter gradients (summed per species pair and
+    taken back through the mixing rule) against central differences of L from its force routine, and
+    eps-homogeneity (L is linear in every eps_ab, so sum_t eps_t dL/deps_t = L)."""
+    wl, G = _adj_case()
+    wl.species = np.random.default_rng(33).integers(0, 3, size=wl.n).astype(np.int32)
+    wl.eps, wl.sigma = np.array([1.0, 0.5, 0.8]), np.array([1.0, 0.88, 0.95])
+    gam = 0.1
+    gx, ge, gs, L = oracle.adjoint(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam)
+    h = 1e-6
+    for which, grad in (("eps", ge), ("sigma", gs)):
+        for p in range(3):
+            e1, s1 = wl.eps.copy(), wl.sigma.copy()
+            e2, s2 = wl.eps.copy(), wl.sigma.copy()
+            if which == "eps":
+                e1[p] += h; e2[p] -= h
+            else:
+                s1[p] += h; s2[p] -= h
+            fd = (oracle.loss(wl.x, wl.species, e1, s1, wl.rcut, wl.mesh.periodic, G, gam)
+                  - oracle.loss(wl.x, wl.species, e2, s2, wl.rcut, wl.mesh.periodic, G, gam)) / (2 * h)
+            assert abs(fd - grad[p]) < 1e-6 * max(1.0, abs(grad[p])), (which, p, fd, grad[p])
+    assert abs((wl.eps * ge).sum() - L) < 1e-10 * abs(L)
+
+
 def test_adjoint_position_fd_and_invariants(oracle):
     wl, G = _adj_case()
     gam = 0.1
