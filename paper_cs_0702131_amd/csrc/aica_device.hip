@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void k_locate_fast(
 // the faces are first tried with the FP32 test, which only accepts points strictly inside.  Otherwise one
 // lane tests the candidates in turn.
 template <bool WAVE>
-__device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restrict__ rec32,
+__device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restrict__ rec32, const float4 *__restrict__ pl32,
                              const int64_t *__restrict__ rec_off, const double *__restrict__ rec,
                              const int64_t *__restrict__ nbr_off, const int32_t *__restrict__ nbr,
                              const double *__restrict__ bb, const int64_t *__restrict__ gb_off,
@@ -493,6 +493,10 @@ __device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restri
   if (h0 >= 0) {
     const int64_t k0 = nbr_off[h0], kc = nbr_off[h0 + 1] - k0 + 1;  // the previous cell and its neighbours
     auto cand = [&](int64_t k) { return k == 0 ? h0 : nbr[k0 + k - 1]; };
+    float4 ball;
+    if (WAVE && pl32)
+      for (int64_t b = 0; b < kc && found < 0; b += kStep)
+        round(b, kc, cand, [&](int32_t c) { return plane_ball(p, rec32 + (int64_t)kR32 * c, pl32 + (int64_t)kPl * c, ball); });
     if (WAVE && rec32)
       for (int64_t b = 0; b < kc && found < 0; b += kStep)
         round(b, kc, cand, [&](int32_t c) { return surely_in_rec32(p, rec32 + (int64_t)kR32 * c); });
@@ -504,6 +508,16 @@ __device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restri
     if (f0 >= 0 && f1 >= 0 && f2 >= 0 && f0 < (double)nb0 && f1 < (double)nb1 && f2 < (double)nb2) {
       const int64_t bin = (int64_t)f0 + nb0 * ((int64_t)f1 + nb1 * (int64_t)f2);
       const int64_t g0 = gb_off[bin], g1 = gb_off[bin + 1];
+      // a cell whose planes show the point strictly inside is the only cell that holds it
+      if (pl32) {
+        float4 ball;
+        for (int64_t b = 0; b < g1 - g0 && found < 0; b += kStep)
+          round(b, g1 - g0, [&](int64_t k) { return gb_cell[g0 + k]; }, [&](int32_t c) {
+            const double *B = bb + 6 * (int64_t)c;
+            if (p[0] < B[0] || p[1] < B[1] || p[2] < B[2] || p[0] > B[3] || p[1] > B[4] || p[2] > B[5]) return false;
+            return plane_ball(p, rec32 + (int64_t)kR32 * c, pl32 + (int64_t)kPl * c, ball);
+          });
+      }
       for (int64_t b = 0; b < g1 - g0 && found < 0; b += kStep)
         round(b, g1 - g0, [&](int64_t k) { return gb_cell[g0 + k]; }, [&](int32_t c) {
           const double *B = bb + 6 * (int64_t)c;
@@ -537,7 +551,7 @@ __global__ __launch_bounds__(256) void k_locate_slow(
     const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
     int32_t found = -1;
     if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))
-      found = slow_find<WAVE>(p, hint ? hint[t] : -1, rec32, rec_off, rec, nbr_off, nbr, bb, gb_off, gb_cell, glo0,
+      found = slow_find<WAVE>(p, hint ? hint[t] : -1, rec32, pl32, rec_off, rec, nbr_off, nbr, bb, gb_off, gb_cell, glo0,
                               glo1, glo2, gh, nb0, nb1, nb2);
     if (!WAVE || (threadIdx.x & 63) == 0) {
       cell_t[t] = found;
