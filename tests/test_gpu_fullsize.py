@@ -85,3 +85,47 @@ def test_channel_full_size(A, oracle):
     _note(f"  adjoint on {len(arows)} rows: fp32 {err32:.3e}, fp64 {err64:.3e} ({time.time() - t0:.1f}s)")
     assert err32 < 1e-6
     assert err64 < 1e-12
+
+
+def test_wedge_full_size(A, oracle):
+    """The rotating-referral benchmark workload at full size (one of 12 sectors of the annulus r 100-200,
+    Lz 60: 371,896 molecules, 373,500 cells, contacts down to about 0.73 sigma): forces in both precisions
+    on sampled rows against the oracle (each row summed over every molecule and every image of the rotation
+    group and the z translation), equal pair counts, dL/dx on sampled rows against the oracle, and the FP32
+    adjoint against the FP64 path on every row."""
+    import torch
+    t0 = time.time()
+    wl = W.wedge(seed=16, r0=100.0, r1=200.0, n_sectors=12, Lz=60.0, nr=83, nphi=90, nz=50, density=0.8)
+    d = A.DIL(wl.mesh, wl.rcut)
+    _note(f"wedge: {wl.n} molecules, {wl.mesh.n_cells} cells, lists built ({time.time() - t0:.1f}s)")
+    rows = np.random.default_rng(53).choice(wl.n, 256, replace=False)
+    Fr, Ur, Wr, cnt = oracle.forces_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, rows,
+                                         rot=wl.rotations)
+    rms = np.sqrt((Fr ** 2).sum(1).mean())
+    G = W.qround(np.random.default_rng(54).standard_normal((wl.n, 3)))
+    gam = 0.1
+    arows = rows[:128]
+    rg = oracle.adjoint_rows(wl.x, wl.species, wl.eps, wl.sigma, wl.rcut, wl.mesh.periodic, G, gam, arows,
+                             rot=wl.rotations)
+    grms = np.sqrt((rg ** 2).mean())
+    _note(f"oracle rows done ({time.time() - t0:.1f}s)")
+    npairs, gx = {}, {}
+    for prec, tol, atol, dt in (("fp32", 1e-5, 1e-6, torch.float32), ("fp64", 1e-12, 1e-12, torch.float64)):
+        x = torch.tensor(wl.x, dtype=dt, device="cuda")
+        A.aica_bin(d, x)
+        F, uw, n = A.aica_forces(d, x, None, wl.eps, wl.sigma, precision=prec)
+        g, _, _ = A.aica_forces_adjoint(d, x, torch.tensor(G, dtype=dt, device="cuda"), gam, None, wl.eps,
+                                        wl.sigma, precision=prec)
+        torch.cuda.synchronize()
+        F = F.double().cpu().numpy()
+        gx[prec] = g.double().cpu().numpy()
+        npairs[prec] = int(n.cpu()[0])
+        err = np.sqrt(((F[rows] - Fr) ** 2).sum(1)).max() / rms
+        aerr = np.abs(gx[prec][arows] - rg).max() / grms
+        _note(f"  {prec}: sampled e_F {err:.3e}, dL/dx on {len(arows)} rows {aerr:.3e}, npairs {npairs[prec]}")
+        assert err < tol and aerr < atol
+    assert npairs["fp32"] == npairs["fp64"]
+    g64 = gx["fp64"]
+    eall = np.abs(gx["fp32"] - g64).max() / np.sqrt((g64 ** 2).mean())
+    _note(f"  FP32 dL/dx against the FP64 path over all {wl.n} rows: {eall:.3e} ({time.time() - t0:.1f}s)")
+    assert eall < 1e-6
