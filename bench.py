@@ -249,8 +249,8 @@ def pmc_summary(paths, calib_fetch=None, calib_write=None, calib_mib=512):
             for r in csv.DictReader(fh):
                 k = re.sub(r"\(.*", "", r["Kernel_Name"].replace("void (anonymous namespace)::", "")
                            .replace("(anonymous namespace)::", ""))
-                acc.setdefault(k, {}).setdefault(r["Counter_Name"], {})[r["Dispatch_Id"]] = (
-                    acc.get(k, {}).get(r["Counter_Name"], {}).get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"]))
+                per = acc.setdefault(k, {}).setdefault(r["Counter_Name"], {})
+                per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
                 dur.setdefault(k, {})[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
         return acc, dur
     acc, dur = {}, {}
