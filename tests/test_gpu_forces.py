@@ -90,6 +90,17 @@ def test_small_random_both_precisions(A, oracle, seed, periodic, species):
     check_case(A, oracle, wl, "fp32", 1e-5, 1e-6)
 
 
+@pytest.mark.parametrize("nsp", [3, 8])
+def test_many_species(A, oracle, nsp):
+    """Mixtures of three and eight species (the largest the library takes; parameters looked up per pair
+    from the Lorentz-Berthelot table): forces, U, W and the pair set against the oracle in both precisions."""
+    wl = W.small_random(n_mesh=(4, 3, 5), L=(8.5, 7.0, 9.0), N=300, seed=70 + nsp)
+    wl.species = np.random.default_rng(80 + nsp).integers(0, nsp, size=wl.n).astype(np.int32)
+    wl.eps, wl.sigma = np.linspace(1.0, 0.4, nsp), np.linspace(1.0, 0.8, nsp)
+    check_case(A, oracle, wl, "fp64", 1e-12, 1e-12)
+    check_case(A, oracle, wl, "fp32", 1e-5, 1e-6)
+
+
 @pytest.mark.parametrize("seed,periodic", [(5, (0, 1, 2)), (6, (1,))])
 def test_pair_counts_per_molecule(A, oracle, seed, periodic):
     """aica_pair_counts against the oracle's pair list: every pair counts once for each member, a molecule
