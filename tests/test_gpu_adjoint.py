@@ -122,9 +122,13 @@ def test_adjoint_vs_finite_differences(A, oracle):
         assert checked >= 20
 
 
-def test_autograd_gradcheck(A):
+@pytest.mark.parametrize("nsp", [2, 3])
+def test_autograd_gradcheck(A, nsp):
     import torch
     wl = W.small_random(n_mesh=(3, 3, 3), L=(7.0, 7.0, 7.0), N=40, seed=51, species_frac=0.6, min_sep=0.9)
+    if nsp == 3:
+        wl.species = np.random.default_rng(52).integers(0, 3, size=wl.n).astype(np.int32)
+        wl.eps, wl.sigma = np.array([1.0, 0.5, 0.75]), np.array([1.0, 0.88, 0.94])
     d = A.DIL(wl.mesh, wl.rcut)
     x = torch.tensor(wl.x, dtype=torch.float64, device="cuda", requires_grad=True)
     eps = torch.tensor(wl.eps, dtype=torch.float64, requires_grad=True)
