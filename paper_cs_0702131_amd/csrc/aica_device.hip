@@ -347,7 +347,7 @@ __device__ bool plane_ball(const double *p, const float4 *R, const float4 *PL, f
 // ball kept from its last record test is in its previous cell (hint); the others are compacted in LDS and
 // tested 64 at a time against the FP32 records (the previous cell, then the cell across the face most
 // likely crossed: a molecule that a record shows strictly inside a cell is in no other); every other
-// molecule goes to a list.  k_locate_slow takes that list, one wave per molecule: the FP64 previous-cell
+// molecule goes to a list.  k_locate_slow takes that list, 16 lanes per molecule: the FP64 previous-cell
 // test and the cells across the previous cell's faces (a molecule that left its cell has crossed one of
 // them: the paper's membership tracking), each accepted only when the point is strictly inside; then
 // every cell whose padded box holds the point, in ascending mesh cell id (the lowest containing cell wins
@@ -460,10 +460,12 @@ __global__ __launch_bounds__(256) void k_locate_fast(
 // The slow path for one molecule at p with previous cell h0 (-1: none): the previous cell and the cells
 // across its faces, each accepted only when p is strictly inside (so at most one accepts), then the cells of
 // the background bin whose padded box holds p, in ascending mesh cell id, the first containing one.  WAVE:
-// the wave's lanes test up to 64 candidates side by side (the lowest accepting lane is the first accepting
-// candidate, so the answer is that of testing them one after another); with FP32 records the cells across
-// the faces are first tried with the FP32 test, which only accepts points strictly inside.  Otherwise one
-// lane tests the candidates in turn.
+// a group of kSlowLanes lanes (four molecules per wave) tests that many candidates side by side (the lowest
+// accepting lane is the first accepting candidate, so the answer is that of testing them one after another);
+// every branch below depends only on values shared by the group, so its lanes stay together.  With FP32
+// records the cells across the faces are first tried with the FP32 test, which only accepts points strictly
+// inside.  Otherwise one lane tests the candidates in turn.
+constexpr int kSlowLanes = 16;
 template <bool WAVE>
 __device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restrict__ rec32, const float4 *__restrict__ pl32,
                              const int64_t *__restrict__ rec_off, const double *__restrict__ rec,
@@ -471,8 +473,9 @@ __device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restri
                              const double *__restrict__ bb, const int64_t *__restrict__ gb_off,
                              const int32_t *__restrict__ gb_cell, double glo0, double glo1, double glo2, double gh,
                              int64_t nb0, int64_t nb1, int64_t nb2) {
-  constexpr int kStep = WAVE ? 64 : 1;
-  const int lane = WAVE ? (int)(threadIdx.x & 63) : 0;
+  constexpr int kStep = WAVE ? kSlowLanes : 1;
+  const int lane = WAVE ? (int)(threadIdx.x & (kSlowLanes - 1)) : 0;
+  const int g0lane = WAVE ? (int)(threadIdx.x & 63) - lane : 0;  // first lane of this molecule's group
   int32_t found = -1;
   // one round of candidate tests: k-th candidate c(k) for k < kc, test(c) -> accepted
   auto round = [&](int64_t b, int64_t kc, auto cand, auto test) {
@@ -484,8 +487,8 @@ __device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restri
       in = test(c);
     }
     if constexpr (WAVE) {
-      const unsigned long long m = __builtin_amdgcn_ballot_w64(in);
-      if (m) found = __shfl(c, (int)__builtin_ctzll(m), 64);
+      const unsigned long long m = (__builtin_amdgcn_ballot_w64(in) >> g0lane) & ((1ull << kSlowLanes) - 1);
+      if (m) found = __shfl(c, g0lane + (int)__builtin_ctzll(m), 64);
     } else if (in) {
       found = c;
     }
@@ -529,9 +532,9 @@ __device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restri
   return found;
 }
 
-// The slow kernel.  WAVE (molecules that have a previous cell): one wave per molecule; otherwise (the first
-// binning, where every molecule comes here) one thread per molecule.  A fixed grid strides over the list,
-// whose length is only known on the device.
+// The slow kernel.  WAVE (molecules that have a previous cell): kSlowLanes lanes per molecule; otherwise (the
+// first binning, where every molecule comes here) one thread per molecule.  A fixed grid strides over the
+// list, whose length is only known on the device.
 template <typename PT, bool WAVE>
 __global__ __launch_bounds__(256) void k_locate_slow(
     const PT *__restrict__ pos, const unsigned long long *__restrict__ nslow, const int32_t *__restrict__ slow,
@@ -544,8 +547,9 @@ __global__ __launch_bounds__(256) void k_locate_slow(
     int32_t *__restrict__ count, unsigned long long *__restrict__ status) {
   const int64_t ns = (int64_t)*nslow;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gsize = (int64_t)gridDim.x * blockDim.x;
-  const int64_t u0 = WAVE ? gid >> 6 : gid, ustep = WAVE ? gsize >> 6 : gsize;
-  for (int64_t u = u0; u < ns; u += ustep) {  // wave-uniform with WAVE
+  constexpr int kSh = __builtin_ctz(kSlowLanes);
+  const int64_t u0 = WAVE ? gid >> kSh : gid, ustep = WAVE ? gsize >> kSh : gsize;
+  for (int64_t u = u0; u < ns; u += ustep) {  // uniform in each lane group with WAVE
     const int64_t t = slow[u];
     const int64_t i = trav ? trav[t] : t;
     const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
@@ -553,7 +557,7 @@ __global__ __launch_bounds__(256) void k_locate_slow(
     if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))
       found = slow_find<WAVE>(p, hint ? hint[t] : -1, rec32, pl32, rec_off, rec, nbr_off, nbr, bb, gb_off, gb_cell, glo0,
                               glo1, glo2, gh, nb0, nb1, nb2);
-    if (!WAVE || (threadIdx.x & 63) == 0) {
+    if (!WAVE || (threadIdx.x & (kSlowLanes - 1)) == 0) {
       cell_t[t] = found;
       // the ball about p inside the cell found, when the plane test shows p that far inside; else no ball
       // until the next record test in this cell
