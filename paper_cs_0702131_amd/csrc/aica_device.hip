@@ -459,22 +459,22 @@ __global__ __launch_bounds__(256) void k_locate_fast(
 
 // The slow path for one molecule at p with previous cell h0 (-1: none): the previous cell and the cells
 // across its faces, each accepted only when p is strictly inside (so at most one accepts), then the cells of
-// the background bin whose padded box holds p, in ascending mesh cell id, the first containing one.  WAVE:
-// a group of kSlowLanes lanes (four molecules per wave) tests that many candidates side by side (the lowest
-// accepting lane is the first accepting candidate, so the answer is that of testing them one after another);
-// every branch below depends only on values shared by the group, so its lanes stay together.  With FP32
-// records the cells across the faces are first tried with the FP32 test, which only accepts points strictly
-// inside.  Otherwise one lane tests the candidates in turn.
-constexpr int kSlowLanes = 16;
-template <bool WAVE>
+// the background bin whose padded box holds p, in ascending mesh cell id, the first containing one.  LANES
+// (16 or 64) > 1: a group of that many lanes (a whole wave, or four molecules per wave) tests that many
+// candidates side by side (the lowest accepting lane is the first accepting candidate, so the answer is that
+// of testing them one after another); every branch below depends only on values shared by the group, so its
+// lanes stay together.  With FP32 records the cells across the faces are first tried with the FP32 test,
+// which only accepts points strictly inside.  LANES = 1: one lane tests the candidates in turn.
+template <int LANES>
 __device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restrict__ rec32, const float4 *__restrict__ pl32,
                              const int64_t *__restrict__ rec_off, const double *__restrict__ rec,
                              const int64_t *__restrict__ nbr_off, const int32_t *__restrict__ nbr,
                              const double *__restrict__ bb, const int64_t *__restrict__ gb_off,
                              const int32_t *__restrict__ gb_cell, double glo0, double glo1, double glo2, double gh,
                              int64_t nb0, int64_t nb1, int64_t nb2) {
-  constexpr int kStep = WAVE ? kSlowLanes : 1;
-  const int lane = WAVE ? (int)(threadIdx.x & (kSlowLanes - 1)) : 0;
+  constexpr bool WAVE = LANES > 1;
+  constexpr int kStep = LANES;
+  const int lane = WAVE ? (int)(threadIdx.x & (LANES - 1)) : 0;
   const int g0lane = WAVE ? (int)(threadIdx.x & 63) - lane : 0;  // first lane of this molecule's group
   int32_t found = -1;
   // one round of candidate tests: k-th candidate c(k) for k < kc, test(c) -> accepted
@@ -487,7 +487,8 @@ __device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restri
       in = test(c);
     }
     if constexpr (WAVE) {
-      const unsigned long long m = (__builtin_amdgcn_ballot_w64(in) >> g0lane) & ((1ull << kSlowLanes) - 1);
+      const unsigned long long m =
+          LANES == 64 ? __builtin_amdgcn_ballot_w64(in) : (__builtin_amdgcn_ballot_w64(in) >> g0lane) & ((1ull << LANES) - 1);
       if (m) found = __shfl(c, g0lane + (int)__builtin_ctzll(m), 64);
     } else if (in) {
       found = c;
@@ -532,10 +533,12 @@ __device__ int32_t slow_find(const double *p, int32_t h0, const float4 *__restri
   return found;
 }
 
-// The slow kernel.  WAVE (molecules that have a previous cell): kSlowLanes lanes per molecule; otherwise (the
-// first binning, where every molecule comes here) one thread per molecule.  A fixed grid strides over the
-// list, whose length is only known on the device.
-template <typename PT, bool WAVE>
+// The slow kernel.  Molecules that have a previous cell: LANES (16 or 64) lanes per molecule; otherwise (the
+// first binning, where every molecule comes here) LANES = 1, one thread per molecule.  A fixed grid strides
+// over the list, whose length is only known on the device.  A group of 16 lanes keeps four molecules in
+// flight per wave, which pays when the list is longer than the grid's waves; with fewer molecules a whole
+// wave per molecule ends sooner (a wave of four molecules runs their different paths one after another).
+template <typename PT, int LANES>
 __global__ __launch_bounds__(256) void k_locate_slow(
     const PT *__restrict__ pos, const unsigned long long *__restrict__ nslow, const int32_t *__restrict__ slow,
     const int32_t *__restrict__ trav, const int32_t *__restrict__ hint, const float4 *__restrict__ rec32,
@@ -547,17 +550,17 @@ __global__ __launch_bounds__(256) void k_locate_slow(
     int32_t *__restrict__ count, unsigned long long *__restrict__ status) {
   const int64_t ns = (int64_t)*nslow;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gsize = (int64_t)gridDim.x * blockDim.x;
-  constexpr int kSh = __builtin_ctz(kSlowLanes);
-  const int64_t u0 = WAVE ? gid >> kSh : gid, ustep = WAVE ? gsize >> kSh : gsize;
-  for (int64_t u = u0; u < ns; u += ustep) {  // uniform in each lane group with WAVE
+  constexpr int kSh = __builtin_ctz(LANES);
+  const int64_t u0 = gid >> kSh, ustep = gsize >> kSh;
+  for (int64_t u = u0; u < ns; u += ustep) {  // uniform in each lane group
     const int64_t t = slow[u];
     const int64_t i = trav ? trav[t] : t;
     const double p[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
     int32_t found = -1;
     if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))
-      found = slow_find<WAVE>(p, hint ? hint[t] : -1, rec32, pl32, rec_off, rec, nbr_off, nbr, bb, gb_off, gb_cell, glo0,
+      found = slow_find<LANES>(p, hint ? hint[t] : -1, rec32, pl32, rec_off, rec, nbr_off, nbr, bb, gb_off, gb_cell, glo0,
                               glo1, glo2, gh, nb0, nb1, nb2);
-    if (!WAVE || (threadIdx.x & (kSlowLanes - 1)) == 0) {
+    if ((threadIdx.x & (LANES - 1)) == 0) {
       cell_t[t] = found;
       // the ball about p inside the cell found, when the plane test shows p that far inside; else no ball
       // until the next record test in this cell
@@ -1316,11 +1319,14 @@ int aica_bin(aica_dil *h, const void *pos_dev, int32_t pos_dtype, int64_t n, voi
     const float4 *pl = h->has_rec32 ? h->d_pl32.as<float4>() : nullptr;
     int32_t *slow = h->d_slow.as<int32_t>();
     unsigned long long *nslow = status + 2;
+    // lanes per molecule of the slow kernel: a whole wave, or 16 (four molecules per wave) when the previous
+    // binning sent more molecules down the slow path than the grid below has waves
+    const bool slow16 = prev && h->located[2] > 4 * 2048;
 #define AICA_LOCATE(PT)                                                                                            \
   hipLaunchKernelGGL((k_locate_fast<PT>), dim3(grid1d(n, 256 * kLocPerLane)), dim3(256), 0, st, (const PT *)pos_dev, \
                      n, trav, hint, r32, pl, h->d_ref.as<float4>(), h->d_cell_of.as<int32_t>(), h->d_rank.as<int32_t>(), \
                      h->d_count.as<int32_t>(), nslow, slow, routes);                                               \
-  hipLaunchKernelGGL(prev ? (k_locate_slow<PT, true>) : (k_locate_slow<PT, false>),                              \
+  hipLaunchKernelGGL(!prev ? (k_locate_slow<PT, 1>) : slow16 ? (k_locate_slow<PT, 16>) : (k_locate_slow<PT, 64>), \
                      dim3(std::min<int64_t>(prev ? grid1d(n, 4) : grid1d(n, 256), 2048)), dim3(256), 0, st,        \
                      (const PT *)pos_dev, nslow, slow, trav, hint, r32, pl, h->d_rec_off.as<int64_t>(),          \
                      h->d_rec.as<double>(), h->d_nbr_off.as<int64_t>(),                                            \
