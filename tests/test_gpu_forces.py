@@ -415,7 +415,39 @@ def test_binning_balls_and_routes(A, oracle):
     assert moved > 20 and routes[5][2] < 0.5 * moved
 
 
-def test_cells_at_the_occupancy_limit(A, oracle):
+def test_binning_slow_path_lane_groups(A, oracle):
+    """The slow location kernel takes a molecule on 16 lanes (four per wave) when the previous binning sent
+    more molecules down the slow path than its grid has waves (8,192), else on a whole wave.  12,000 molecules
+    at random on a jittered, shuffled mesh: the first binning searches for every one of them, so the second
+    (after moves of up to 0.9 per axis, so that many molecules land in cells that are not across a face)
+    runs the 16-lane groups, and the third (small moves) whole waves unless the second sent more than 8,192
+    molecules down the slow path.  Every binning equals brute-force location, in both position precisions."""
+    import torch
+    Ls = [float(W.qround(v)) for v in (36.0, 24.0, 30.0)]
+    nodes = [W.uniform_nodes(Ls[a], n) for a, n in enumerate((18, 12, 15))]
+    mesh = W.jitter_interior(W.hex_mesh(*nodes, periodic_axes=(0, 1, 2)), *nodes, 0.25,
+                             np.random.default_rng(41))
+    mesh = W.renumber_cells(mesh, np.random.default_rng(42).permutation(mesh.n_cells))
+    hi = np.array(Ls)
+    rng = np.random.default_rng(43)
+    x0 = W.qround(rng.uniform(0.0, 1.0, size=(12000, 3)) * hi)
+    x0 = np.minimum(x0, hi - W.Q)
+    for dt in (torch.float64, torch.float32):
+        d = A.DIL(mesh, 2.5)
+        x = x0.copy()
+        slow = []
+        for step, amp in enumerate((0.0, 0.9, 0.05)):
+            if amp > 0:
+                x = W.qround(W.wrap(x + rng.uniform(-amp, amp, size=x.shape), np.zeros(3), hi, (0, 1, 2)))
+                x = np.minimum(x, hi - W.Q)
+            A.aica_bin(d, torch.tensor(x, dtype=dt, device="cuda"))
+            cell_of, _, _ = A.aica_bin_export(d, len(x))
+            assert np.array_equal(cell_of, oracle.locate(mesh, x)), (dt, step)
+            slow.append(d.info()["located_search"])
+        d.close()
+        _note(f"slow-path molecules per binning ({dt}): {slow}")
+        assert slow[0] == len(x0) > 8192  # so the second binning takes the 16-lane groups
+        assert slow[1] > 0  # ... and gives them work
     """Eight cells of 190 molecules each: in the FP64 forward (segments of 192 expanded j) a neighbour
     cell never fits beside the j carried over from the previous segment, so segment boundaries take the
     path that first evaluates the carried j on their own, and neighbour cells are split across segments;
