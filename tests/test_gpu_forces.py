@@ -448,6 +448,9 @@ def test_binning_slow_path_lane_groups(A, oracle):
         _note(f"slow-path molecules per binning ({dt}): {slow}")
         assert slow[0] == len(x0) > 8192  # so the second binning takes the 16-lane groups
         assert slow[1] > 0  # ... and gives them work
+
+
+def test_cells_at_the_occupancy_limit(A, oracle):
     """Eight cells of 190 molecules each: in the FP64 forward (segments of 192 expanded j) a neighbour
     cell never fits beside the j carried over from the previous segment, so segment boundaries take the
     path that first evaluates the carried j on their own, and neighbour cells are split across segments;
