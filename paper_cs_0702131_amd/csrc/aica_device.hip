@@ -347,7 +347,7 @@ __device__ bool plane_ball(const double *p, const float4 *R, const float4 *PL, f
 // ball kept from its last record test is in its previous cell (hint); the others are compacted in LDS and
 // tested 64 at a time against the FP32 records (the previous cell, then the cell across the face most
 // likely crossed: a molecule that a record shows strictly inside a cell is in no other); every other
-// molecule goes to a list.  k_locate_slow takes that list, 16 lanes per molecule: the FP64 previous-cell
+// molecule goes to a list.  k_locate_slow takes that list, a group of lanes per molecule: the FP64 previous-cell
 // test and the cells across the previous cell's faces (a molecule that left its cell has crossed one of
 // them: the paper's membership tracking), each accepted only when the point is strictly inside; then
 // every cell whose padded box holds the point, in ascending mesh cell id (the lowest containing cell wins
