@@ -122,6 +122,9 @@ def aica_bin(dil: DIL, pos):
 def _params(rcut, eps, sigma, precision, compensated):
     eps = _c(np.atleast_1d(np.asarray(eps, dtype=np.float64)), np.float64)
     sig = _c(np.atleast_1d(np.asarray(sigma, dtype=np.float64)), np.float64)
+    # the library reads n_species entries of both arrays
+    if eps.ndim != 1 or sig.shape != eps.shape:
+        raise ValueError("eps and sigma must be 1-D with one entry per species each")
     p = aica_params()
     p.rcut = float(rcut)
     p.n_species = len(eps)

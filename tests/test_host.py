@@ -216,3 +216,14 @@ def test_adjoint_rejects_bad_grad_forces():
                 np.zeros((10, 3))):                                   # not a tensor
         with pytest.raises(ValueError):
             pkg._check_grad_forces(bad, pos)
+
+
+def test_params_reject_mismatched_species_tables():
+    """eps and sigma are read for every species: tables of different lengths (or not 1-D) are refused before
+    the library sees them."""
+    import paper_cs_0702131_amd as pkg
+    p, keep = pkg._params(2.5, (1.0, 0.5), (1.0, 0.88), "fp32", True)
+    assert p.n_species == 2
+    for eps, sig in (((1.0, 0.5), (1.0,)), ((1.0,), (1.0, 0.88)), (np.ones((2, 2)), np.ones((2, 2)))):
+        with pytest.raises(ValueError):
+            pkg._params(2.5, eps, sig, "fp64", True)
